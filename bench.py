@@ -1,0 +1,168 @@
+"""Throughput benchmark: visibility x component evaluations per second.
+
+Workload: the MWA-like predict (128 tiles = 8128 baselines, 14 times at 8 s,
+32 channels of 80 kHz at 182 MHz; 20000 points, 2000 Gaussians, 2 shapelets
+with n1 + n2 <= 54; Gaussian primary beam), synthetic and seeded.  A step is
+one vp_predict of the whole sky into resident complex64 visibilities on the
+mixed-precision path; the FP64 path is timed beside it.  Shapelets count as
+their (N+1)(N+2)/2 basis functions.
+
+The JSON line carries:
+  roofline     -- the point/Gaussian tile kernel (the dominant kernel here),
+                  vector-ALU bound: algorithmic VALU issue slots per launch /
+                  its mean duration (HIP events on the launch stream) against
+                  the chip's VALU issue peak;
+  cpu_baseline -- the FP64 oracle on a bounded sample of rows, on the host's
+                  cores, which also checks the GPU output on those rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic VALU issue slots per evaluation (transcendentals issue at half rate):
+#   point:    phase scale 1 + reduction 1 + convert 1 + sin 2 + cos 2 + complex MAC 2 = 9
+#   Gaussian: point + exponent scale 1 + exp2 2 + flux x envelope 1              = 13
+#   per (row, component): u l + v m + w (n - 1), 3 FMAs shared by the row's channels
+SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 9, 13, 3
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--cpu-rows", type=int, default=8192)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how "
+              "the work would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2005_09316_amd import vp
+
+    t_gen = time.time()
+    obs, sky = synth.make_config(1)
+    _log("workload generated in %.1f s: %d vis, %d points, %d gaussians, %d shapelets (%d basis)"
+         % (time.time() - t_gen, obs.n_vis, sky.n_point, sky.n_gauss, sky.n_shp, sky.n_basis()))
+    n_vis = obs.n_vis
+    nominal = n_vis * sky.nominal_components()
+    nrows, K = obs.n_time * obs.n_bl, obs.n_chan
+
+    ctx = vp.vp_create_ctx(0, 0)
+    oh, sh = vp.vp_create_obs(ctx, obs), vp.vp_create_sky(ctx, sky)
+    stream = torch.cuda.current_stream()
+    out = torch.empty((obs.n_time, obs.n_bl, obs.n_chan), dtype=torch.complex64, device="cuda")
+
+    def step(prec, buf, dtype):
+        vp.vp_predict(ctx, sh, oh, prec, dtype, buf.data_ptr(), stream.cuda_stream)
+
+    # ---- mixed path (the measured value) ----
+    for _ in range(args.warmup):
+        step(vp.VP_PREC_MIXED, out, vp.VP_C64)
+    torch.cuda.synchronize()
+    vp.vp_profile(ctx, True)
+    vp.vp_profile_read(ctx)  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(vp.VP_PREC_MIXED, out, vp.VP_C64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    counts, tot_ms = vp.vp_profile_read(ctx)
+    vp.vp_profile(ctx, False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = nominal / (ms_step * 1e-3)
+    pg_ms = tot_ms[1] / max(counts[1], 1)
+    shp_ms = tot_ms[2] / max(counts[2], 1)
+    _log("mixed: %.3f ms/step, %.3e evals/s; pg kernel %.3f ms, shapelet kernel %.3f ms"
+         % (ms_step, value, pg_ms, shp_ms))
+
+    # ---- FP64 path, for the speedup ----
+    out64 = torch.empty((obs.n_time, obs.n_bl, obs.n_chan), dtype=torch.complex128, device="cuda")
+    step(vp.VP_PREC_FP64, out64, vp.VP_C128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        step(vp.VP_PREC_FP64, out64, vp.VP_C128)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
+    value64 = nominal / (ms64 * 1e-3)
+    _log("fp64: %.3f ms/step, %.3e evals/s" % (ms64, value64))
+
+    # ---- roofline of the point/Gaussian kernel ----
+    pg_evals_pt = nrows * K * sky.n_point
+    pg_evals_g = nrows * K * sky.n_gauss
+    slots = (pg_evals_pt * SLOTS_POINT + pg_evals_g * SLOTS_GAUSS
+             + nrows * (sky.n_point + sky.n_gauss) * SLOTS_ROW_COMP)
+    achieved = slots / (pg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_pg_tile<mixed>", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s (VALU issue slots)",
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "kernel_ms": round(pg_ms, 4), "shapelet_kernel_ms": round(shp_ms, 4)}
+
+    # ---- sampled parity + CPU baseline (oracle) ----
+    cpu = None
+    err = None
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(5)
+        rows = np.sort(rng.choice(nrows, args.cpu_rows, replace=False))
+        got = out.reshape(nrows, K)[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        threads = oracle.max_threads()
+        t0 = time.perf_counter()
+        ref = oracle.predict(obs, sky, rows=rows, nthreads=threads)
+        dt = time.perf_counter() - t0
+        err = oracle.error_metric(got, ref, obs, sky)
+        sample_evals = len(rows) * K * sky.nominal_components()
+        cpu = {"value": sample_evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": "%d of %d (time, baseline) rows x all %d channels x all components; %.1f s"
+                         % (len(rows), nrows, K, dt)}
+        _log("oracle: %.3e evals/s on %d threads; sampled error / total flux = %.3e" % (cpu["value"], threads, err))
+
+    vp.vp_destroy_sky(sh)
+    vp.vp_destroy_obs(oh)
+    vp.vp_destroy_ctx(ctx)
+
+    line = {
+        "metric": "vis x component evals/s (mixed precision, err <= 1e-6 vs FP64 oracle)",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 phase)", "data": "synthetic",
+        "config": {"workload": synth.CONFIG_NAMES[1], "n_vis": n_vis,
+                   "components": {"point": sky.n_point, "gaussian": sky.n_gauss, "shapelet": sky.n_shp,
+                                  "shapelet_basis": sky.n_basis()},
+                   "nominal_evals_per_step": nominal, "precision": "mixed", "output": "complex64",
+                   "fp64_path": {"evals_per_s": value64, "ms_per_step": ms64},
+                   "speedup_vs_fp64": value / value64,
+                   "evals_per_s_shapelet_as_one": n_vis * (sky.n_point + sky.n_gauss + sky.n_shp) / (ms_step * 1e-3),
+                   "sampled_err_vs_oracle": err},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

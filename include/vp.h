@@ -1,0 +1,205 @@
+/*
+ * vp.h -- C ABI of libvp, direct-Fourier visibility prediction on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * What is computed (Line et al., "Modelling and peeling extended sources with
+ * shapelets: a Fornax A case study"):
+ *
+ *   V(t,b,k) = sum_j S_j(nu_k) xi_j(u,v) exp(sign 2 pi i (u l_j + v m_j + w (n_j - 1)))
+ *
+ * with (u,v,w) the baseline of (time t, baseline b) in wavelengths at channel
+ * k -- uvw are given once per time step in metres and scaled by nu_k / c
+ * (Sec. 3.2, last paragraph) -- and
+ *   - points:     xi = 1                              (Sec. 3.1, Eq. measure_eq_discrete)
+ *   - Gaussians:  xi = exp(-pi^2/(4 ln2) (kx^2 maj^2 + ky^2 min^2)),
+ *                 kx = cos(pa) v + sin(pa) u, ky = -sin(pa) v + cos(pa) u
+ *                                                     (Sec. 3.2, Eqs. gauss-env, scale-gauss-x/y)
+ *   - shapelets:  xi = sum_{n1+n2<=N} C_{n1,n2} (sign i)^(n1+n2) phi_n1(a) phi_n2(b),
+ *                 a = kappa beta1 (cos(pa) v' + sin(pa) u'),
+ *                 b = kappa beta2 (-sin(pa) v' + cos(pa) u'), kappa = pi / sqrt(2 ln 2),
+ *                 (u',v') the baseline re-phased to the shapelet's own centre,
+ *                 phi_n the orthonormal Hermite functions
+ *                                                     (Sec. 2 Eqs. basis_1D, basis_2D, basis_FT;
+ *                                                      Sec. 3.2 Eqs. shape-env, scale-shape-x/y)
+ *   - flux:       S_j(nu) = S_ref (nu / nu_ref)^alpha * B_j(nu), one spectral
+ *                 index per component (Sec. 4.1); B_j is 1 (flat beam, Sec. 3.1)
+ *                 or an optional Gaussian power pattern about the phase centre,
+ *                 exp(-4 ln2 rho_j^2 / Theta(nu)^2), Theta(nu) = Theta_ref nu_ref_beam / nu.
+ *   - peel:       R = D - V, the residual of Sec. 5.1 with unit gains.
+ *
+ * Conventions: angles in radians, FWHMs and beta as FWHM in radians, PA east of
+ * north, fluxes in Jy, frequencies in Hz.  n - 1 is formed as
+ * -(l^2 + m^2) / (1 + n).  The exponent sign is -1 in the paper; +1 yields the
+ * exact complex conjugate.  Coefficients are used as given (the paper's
+ * C <- C / I convention, Sec. 3.2): no extra prefactor is applied.
+ *
+ * Visibility layout: row-major [n_time][n_bl][n_chan] of interleaved complex
+ * numbers, complex128 (VP_C128: double re, double im) or complex64 (VP_C64).
+ *
+ * Threading: every call is thread-safe; predict/subtract calls that share a
+ * stream are ordered by that stream.  Errors: every call returns a VP_* code;
+ * vp_last_error() returns a thread-local message for the calling thread's
+ * last failure.  Out-parameters are written only on success.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define VP_OK 0
+#define VP_EINVAL (-1)     /* invalid argument (NULL, size <= 0, non-finite, out of range) */
+#define VP_ENOMEM (-2)     /* device or host allocation failed */
+#define VP_EDEVICE (-3)    /* HIP runtime error (including faults of earlier async work) */
+#define VP_EAGAIN (-4)     /* job still pending (vp_poll) */
+#define VP_ECAPACITY (-5)  /* job footprint exceeds the context's HBM budget: never admissible */
+#define VP_ENOTFOUND (-6)  /* unknown ticket */
+#define VP_EBUSY (-7)      /* object still in use by pending jobs */
+
+/* precision paths */
+#define VP_PREC_FP64 0        /* FP64 everywhere (phase, sincos, envelopes, recurrence, contraction, sums) */
+#define VP_PREC_MIXED 1       /* FP64 phase + range reduction; FP32 sincos/envelopes/Kahan sums;
+                                 FP64 Hermite recurrence; FP32 MFMA shapelet contraction */
+#define VP_PREC_MIXED_BF16 2  /* as MIXED, contraction as 3-way BF16 split on MFMA (6 products) */
+#define VP_PREC_FP32 3        /* FP32 everywhere, phase included (reported, not accurate) */
+#define VP_PREC_MIXED_BF16X2 4 /* as MIXED, contraction as 2-way BF16 split (3 products) */
+
+/* output element types */
+#define VP_C128 0
+#define VP_C64 1
+
+/* serving job kinds */
+#define VP_JOB_PREDICT 0
+#define VP_JOB_SUBTRACT 1
+
+/* maximum shapelet order n1 + n2 */
+#define VP_NMAX_LIMIT 96
+
+typedef struct vp_ctx vp_ctx;
+typedef struct vp_obs vp_obs;
+typedef struct vp_sky vp_sky;
+
+/* Observation (Sec. 3.2: uvw once per time step; channels scale it by nu/c). */
+typedef struct {
+  int32_t n_time, n_bl, n_chan;
+  const double *uvw_m;   /* host, [n_time][n_bl][3] baseline (u,v,w) in metres */
+  const double *freq_hz; /* host, [n_chan] channel frequencies */
+  double ra0, dec0;      /* phase centre, rad */
+  int32_t sign;          /* exponent sign: -1 (paper) or +1 */
+  double beam_fwhm_rad;  /* Gaussian power-beam FWHM at beam_nu_ref_hz; 0 => flat beam */
+  double beam_nu_ref_hz;
+} vp_obs_desc;
+
+/* Sky model (Sec. 3.1 points; Sec. 3.2 Gaussians and shapelets; Sec. 4.1 spectra).
+ * Shapelet coefficients are packed per shapelet, n1-major: n1 = 0..N, then
+ * n2 = 0..N-n1, (N+1)(N+2)/2 values starting at coeffs[s_coeff_off[s]]. */
+typedef struct {
+  double nu_ref_hz; /* reference frequency of S_ref */
+  int32_t n_point;
+  const double *p_ra, *p_dec, *p_sref, *p_alpha;
+  int32_t n_gauss;
+  const double *g_ra, *g_dec, *g_sref, *g_alpha;
+  const double *g_maj, *g_min, *g_pa; /* FWHM major/minor (rad), PA (rad) */
+  int32_t n_shp;
+  const double *s_ra, *s_dec, *s_sref, *s_alpha;
+  const double *s_beta1, *s_beta2, *s_pa; /* beta as FWHM of the (0,0) basis (rad), PA (rad) */
+  const int32_t *s_nmax;                  /* N = max(n1 + n2) per shapelet, 0..VP_NMAX_LIMIT */
+  const int64_t *s_coeff_off;             /* offset of each shapelet's coefficients */
+  const double *coeffs;
+} vp_sky_desc;
+
+/* Create a context on HIP device `hip_device`.  hbm_budget_bytes bounds the
+ * device memory that admitted serving jobs may hold at once (library tables
+ * plus each job's visibility buffer); 0 selects 90% of the device's free
+ * memory.  Errors: VP_EINVAL (bad device / NULL out), VP_EDEVICE. */
+int vp_create_ctx(int hip_device, uint64_t hbm_budget_bytes, vp_ctx **out);
+
+/* Destroy a context.  Fails with VP_EBUSY while serving jobs are pending;
+ * observations and skies still alive are destroyed with it. */
+int vp_destroy_ctx(vp_ctx *ctx);
+
+/* Copy an observation to the device.  Host arrays are read during the call
+ * and may be freed on return.  Errors: VP_EINVAL for n <= 0, NULL arrays,
+ * non-finite uvw/frequencies, frequencies <= 0, |sign| != 1, beam FWHM < 0 or
+ * a positive FWHM with beam_nu_ref_hz <= 0; VP_ENOMEM; VP_EDEVICE. */
+int vp_create_obs(vp_ctx *ctx, const vp_obs_desc *desc, vp_obs **out);
+int vp_destroy_obs(vp_obs *obs); /* VP_EBUSY while a pending job uses it */
+
+/* Copy a sky model to the device.  Host arrays are read during the call and
+ * may be freed on return.  Per-(sky, observation) tables (direction cosines,
+ * frames, flux per channel, coefficient tiles) are built on the device by the
+ * first predict/subtract that pairs them, and cached.  Errors: VP_EINVAL for
+ * negative counts, NULL arrays with a positive count, non-finite values,
+ * nu_ref <= 0, Gaussian FWHM < 0, beta <= 0, nmax outside 0..VP_NMAX_LIMIT,
+ * coefficient offsets < 0; VP_ENOMEM; VP_EDEVICE. */
+int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *desc, vp_sky **out);
+int vp_destroy_sky(vp_sky *sky); /* VP_EBUSY while a pending job uses it */
+
+/* Predict: write V[n_time][n_bl][n_chan] (interleaved complex, `dtype`) into
+ * caller-owned device memory `vis_dev`, asynchronously on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  `precision` is a VP_PREC_* path.
+ * Returns once the work is enqueued; faults of the asynchronous work surface
+ * as VP_EDEVICE from a later call.  Errors: VP_EINVAL, VP_EDEVICE, VP_ENOMEM. */
+int vp_predict(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype,
+               void *vis_dev, void *hip_stream);
+
+/* Subtract (peel with unit gains): data <- data - V, in place on caller-owned
+ * device memory laid out as for vp_predict.  Same errors. */
+int vp_subtract(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype,
+                void *data_dev, void *hip_stream);
+
+/* Serving (continuous batching). */
+typedef struct {
+  int32_t kind; /* VP_JOB_PREDICT or VP_JOB_SUBTRACT */
+  const vp_sky *sky;
+  const vp_obs *obs;
+  int32_t precision, dtype;
+  void *vis_dev;          /* caller-owned device buffer, alive until the job is done */
+  uint64_t t_arrival_ns;  /* caller's arrival timestamp (CLOCK_MONOTONIC ns); 0 => now */
+} vp_job;
+
+typedef struct {
+  int32_t status;   /* VP_OK or the job's error code */
+  uint64_t t_submit, t_admit, t_start, t_done; /* CLOCK_MONOTONIC ns */
+} vp_job_result;
+
+/* Enqueue a job; returns a ticket.  The job is admitted when its HBM footprint
+ * fits the budget minus what admitted jobs hold, in FIFO order; admitted jobs
+ * are expanded into tiles that a persistent device kernel processes together
+ * with the tiles of other admitted jobs.  Errors: VP_EINVAL, VP_ECAPACITY if
+ * the footprint exceeds the whole budget.  Thread-safe. */
+int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket);
+
+/* Non-blocking: VP_OK with *res filled when the job is done (res->status holds
+ * the job's own result), VP_EAGAIN while pending, VP_ENOTFOUND for an unknown
+ * or already-collected ticket.  A completed ticket is released by the VP_OK
+ * poll.  Thread-safe. */
+int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res);
+
+/* HBM footprint (bytes) that admission charges for `job`.  Errors: VP_EINVAL. */
+int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes);
+
+/* Per-kernel timing, for measurement.  When enabled, the library records HIP
+ * events around each kernel it launches for vp_predict/vp_subtract on the
+ * caller's stream and accumulates their durations by kernel class:
+ * 0 = per-(sky,obs) table build, 1 = point/Gaussian tile kernel,
+ * 2 = shapelet tile kernel.  vp_profile_read synchronises the recorded events,
+ * fills counts[3] and total_ms[3], and resets the accumulators. */
+int vp_profile(vp_ctx *ctx, int enable);
+int vp_profile_read(vp_ctx *ctx, int64_t *counts, double *total_ms);
+
+/* Thread-local message describing the calling thread's last error ("" if none). */
+const char *vp_last_error(void);
+
+/* Library version string. */
+const char *vp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

@@ -1,0 +1,835 @@
+// vp_kernels.hip -- gfx950 kernels of libvp.
+//
+// Direct-Fourier visibility prediction (Line et al., Sec. 3): for every
+// (time, baseline, channel) visibility, sum over point, Gaussian and shapelet
+// components of flux x uv-envelope x phase term (Eqs. measure_eq_discrete,
+// env_visi_def, gauss-env, shape-env).  The work is split in two kernels per
+// call, each over tiles of 256 (time, baseline) rows x a block of channels:
+//
+//   k_pg_tile   points then Gaussians.  One thread owns one row and
+//               kPgChan channels; component lists are staged through LDS in
+//               chunks and read as wave-uniform broadcasts.  Phase per
+//               (row, component) is t0 = u l + v m + w (n-1) in metres (FP64);
+//               per channel t = t0 nu/c, reduced to a fraction of a turn in
+//               FP64, then sin/cos of 2 pi t in FP32 on the transcendental
+//               unit (input in turns).  Sums are plain FP32 over kFlush
+//               components, then Kahan-compensated across those partial sums.
+//   k_shp_mfma  shapelets.  Per (visibility, shapelet): rotate uvw into the
+//               shapelet's frame, run the normalised Hermite recurrence for
+//               both axes (FP64: it costs the same issue slots as FP32 on this
+//               chip and removes the argument-rounding and underflow error of
+//               an FP32 recurrence), contract against the signed coefficient
+//               matrix on MFMA (v_mfma_f32_32x32x2f32: n1 on M, n2 on K,
+//               32 visibilities on N, n2 split by parity into real/imaginary
+//               accumulators, 32-row blocks beyond the n1 + n2 <= N triangle
+//               skipped), finish the n1 sum against the first axis in the
+//               MFMA output layout, and add flux x envelope x phase into a
+//               Kahan accumulator held in LDS.
+//   k_shp_fp64  the FP64 path of the shapelet term on the vector ALU.
+//
+// All arithmetic is done with the exponent sign +1; a sign of -1 is applied
+// by conjugating at the output, which is exact.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "vp_internal.h"
+
+namespace vp {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__constant__ double c_sqn[128];   // sqrt(n)
+__constant__ double c_isqn1[128]; // 1 / sqrt(n + 1)
+
+static constexpr double kPiM14 = 0.75112554446494248285870300477622; // pi^(-1/4)
+static constexpr double kHalfLog2e = 0.72134752044448170367996234050095; // log2(e) / 2
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// The hardware dispatches consecutive workgroups round-robin over the 8 XCDs;
+// give each XCD a contiguous range of logical tiles so that tiles sharing a
+// channel block (and its flux-table rows) share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nt) {
+  const int q = nt >> 3, r = nt & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// cos/sin of 2 pi t for an FP64 phase in turns: exact FP64 reduction to
+// [0, 1), then the FP32 transcendental unit (which takes turns).
+__device__ __forceinline__ void turns_sincos_mixed(double t, float &c, float &s) {
+  const float r = (float)__builtin_amdgcn_fract(t);
+  s = __builtin_amdgcn_sinf(r);
+  c = __builtin_amdgcn_cosf(r);
+}
+
+__device__ __forceinline__ void turns_sincos_f32(float t, float &c, float &s) {
+  const float r = __builtin_amdgcn_fractf(t);
+  s = __builtin_amdgcn_sinf(r);
+  c = __builtin_amdgcn_cosf(r);
+}
+
+__device__ __forceinline__ void turns_sincos_f64(double t, double &c, double &s) {
+  const double r = t - rint(t);  // exact, |r| <= 1/2
+  sincospi(2.0 * r, &s, &c);
+}
+
+template <typename T>
+__device__ __forceinline__ void kahan_add(T &sum, T &cmp, T x) {
+  const T y = x - cmp;
+  const T t = sum + y;
+  cmp = (t - sum) - y;
+  sum = t;
+}
+
+// phi_0 = pi^(-1/4) exp(-x^2/2) with the exponent split into integer and
+// fractional powers of two: the fraction goes through the FP32 exp2 unit, the
+// integer part is applied exactly, so the value keeps full FP32 relative
+// accuracy down to FP64 underflow.
+__device__ __forceinline__ double hermite_phi0_mixed(double x) {
+  const double e = x * x * kHalfLog2e;
+  const double ei = floor(e);
+  const float ef = (float)(e - ei);
+  const double p = (double)__builtin_amdgcn_exp2f(-ef) * kPiM14;
+  return ei > 1100.0 ? 0.0 : ldexp(p, -(int)ei);
+}
+
+// ---------------------------------------------------------------------------
+// per-(sky, observation) tables
+// ---------------------------------------------------------------------------
+
+// Direction cosines of every component relative to the phase centre, the
+// Gaussian envelope's quadratic form, and each shapelet's frame vectors.
+__global__ void k_derive(DeriveArgs a) {
+  const int J = a.P + a.G + a.S;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const double ra = a.ra[j], dec = a.dec[j];
+  const double da = ra - a.ra0;
+  const double sd = sin(dec), cd = cos(dec), sd0 = sin(a.dec0), cd0 = cos(a.dec0);
+  const double sda = sin(da), cda = cos(da);
+  const double l = cd * sda;
+  const double m = sd * cd0 - cd * sd0 * cda;
+  const double n = sd * sd0 + cd * cd0 * cda;
+  const double nm1 = -(l * l + m * m) / (1.0 + n);
+  a.d.pos[j] = make_double4(l, m, nm1, 0.0);
+  if (j >= a.P && j < a.P + a.G) {
+    // exponent of Eq. gauss-env in base 2:
+    //   q = pi^2 / (4 ln2 ln2) * (kx^2 maj^2 + ky^2 min^2),
+    //   kx = cos(pa) v + sin(pa) u, ky = -sin(pa) v + cos(pa) u
+    // expanded in u^2, v^2, u v (metres; the channel scales it by (nu/c)^2).
+    const int g = j - a.P;
+    const double pa = a.g_pa[g], sp = sin(pa), cp = cos(pa);
+    const double M2 = a.g_maj[g] * a.g_maj[g], N2 = a.g_min[g] * a.g_min[g];
+    const double k = 3.14159265358979323846 * 3.14159265358979323846 /
+                     (4.0 * 0.69314718055994530942 * 0.69314718055994530942);
+    a.d.gq[g] = make_double4(k * (sp * sp * M2 + cp * cp * N2),   // u^2
+                             k * (cp * cp * M2 + sp * sp * N2),   // v^2
+                             k * 2.0 * sp * cp * (M2 - N2),       // u v
+                             0.0);
+  } else if (j >= a.P + a.G) {
+    // Shapelet frame: (u', v', w') = T(ra_j, dec_j) T(ra0, dec0)^T (u, v, w),
+    // T's rows being the east, north and pointing unit vectors.  Then
+    // a = kappa beta1 (cos(pa) v' + sin(pa) u'), b = kappa beta2 (cos(pa) u' - sin(pa) v').
+    const int s = j - a.P - a.G;
+    const double sa0 = sin(a.ra0), ca0 = cos(a.ra0), sa = sin(ra), ca = cos(ra);
+    const double T0[3][3] = {{-sa0, ca0, 0.0}, {-sd0 * ca0, -sd0 * sa0, cd0}, {cd0 * ca0, cd0 * sa0, sd0}};
+    const double Tj[2][3] = {{-sa, ca, 0.0}, {-sd * ca, -sd * sa, cd}};
+    double R[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) R[r][c] = Tj[r][0] * T0[c][0] + Tj[r][1] * T0[c][1] + Tj[r][2] * T0[c][2];
+    const double kappa = 3.14159265358979323846 / sqrt(2.0 * 0.69314718055994530942);
+    const double pa = a.s_pa[s], sp = sin(pa), cp = cos(pa);
+    const double ka = kappa * a.s_beta1[s], kb = kappa * a.s_beta2[s];
+    double *f = a.d.sframe + 12 * s;
+    for (int c = 0; c < 3; ++c) {
+      f[c] = ka * (sp * R[0][c] + cp * R[1][c]);
+      f[3 + c] = kb * (cp * R[0][c] - sp * R[1][c]);
+    }
+    f[6] = l; f[7] = m; f[8] = nm1; f[9] = 0.0; f[10] = 0.0; f[11] = 0.0;
+  }
+}
+
+// S_j(nu_k) = S_ref (nu_k / nu_ref)^alpha * B_j(nu_k).
+__global__ void k_flux(FluxArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)a.J * a.Kpad) return;
+  const int j = (int)(idx / a.Kpad), k = (int)(idx % a.Kpad);
+  double S = 0.0;
+  if (k < a.K) {
+    const double nu = a.freq[k];
+    S = a.sref[j] * pow(nu / a.nu_ref, a.alpha[j]);
+    if (a.beam_fwhm > 0.0) {
+      const double4 p = a.d.pos[j];
+      const double rho = asin(sqrt(p.x * p.x + p.y * p.y));
+      const double th = a.beam_fwhm * a.beam_nu_ref / nu;
+      S *= exp(-4.0 * 0.69314718055994530942 * rho * rho / (th * th));
+    }
+  }
+  a.d.flux32[idx] = (float)S;
+  a.d.flux64[idx] = S;
+}
+
+// Coefficient tiles.  Signed coefficients C''[n1][n2] = C[n1][n2] (-1)^floor((n1+n2)/2),
+// so that xi = sum_{n1+n2 even} C'' phi phi + i sum_{n1+n2 odd} C'' phi phi
+// equals sum C i^(n1+n2) phi phi.  Layouts:
+//   a32: [mb][parity][s4][lane]: lane l supplies A[row = l % 32][k = l / 32] of
+//        the MFMA for n1 = 32 mb + l % 32, n2 = 4 s4 + 2 (l / 32) + parity;
+//   c64: [n1][ld], zero outside the triangle;
+//   abf: [part][mb][parity][chunk][lane][8] BF16 hi/mid/lo splits of a32's
+//        values for K = 16 steps: n2 = 32 chunk + 2 (8 (l / 32) + e) + parity.
+__device__ __forceinline__ double signed_coeff(const double *c, int N, int n1, int n2) {
+  if (n1 < 0 || n2 < 0 || n1 > N || n2 > N - n1) return 0.0;
+  const int64_t off = (int64_t)n1 * (N + 1) - (int64_t)n1 * (n1 - 1) / 2;
+  const double v = c[off + n2];
+  return (((n1 + n2) >> 1) & 1) ? -v : v;
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__global__ void k_tiles(TileBuildArgs a) {
+  const int s = blockIdx.y;
+  if (s >= a.S) return;
+  const int N = a.nmax[s];
+  const double *C = a.coeffs + a.coeff_off[s];
+  const int MB = (N + 32) / 32, S4 = (N + 4) / 4;
+  // FP32 MFMA tiles
+  const int n32 = MB * 2 * S4 * 64;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += gridDim.x * blockDim.x) {
+    const int lane = i & 63, rest = i >> 6;
+    const int s4 = rest % S4, mp = rest / S4, par = mp & 1, mb = mp >> 1;
+    const int n1 = 32 * mb + (lane & 31), n2 = 4 * s4 + 2 * (lane >> 5) + par;
+    a.a32[a.a32_off[s] + i] = (float)signed_coeff(C, N, n1, n2);
+  }
+  // FP64 dense
+  const int ld = a.c64_ld[s];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (N + 1) * ld; i += gridDim.x * blockDim.x) {
+    const int n1 = i / ld, n2 = i % ld;
+    a.c64[a.c64_off[s] + i] = signed_coeff(C, N, n1, n2);
+  }
+  // BF16 three-way split tiles
+  const int NC = (N / 2 + 1 + 15) / 16;
+  const int nbf = MB * 2 * NC * 64 * 8;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbf; i += gridDim.x * blockDim.x) {
+    const int e = i & 7, lane = (i >> 3) & 63, rest = i >> 9;
+    const int ch = rest % NC, mp = rest / NC, par = mp & 1, mb = mp >> 1;
+    const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 2 * (8 * (lane >> 5) + e) + par;
+    const float x = (float)signed_coeff(C, N, n1, n2);
+    const uint16_t hi = bf16_rne(x);
+    const float r1 = x - bf16_to_f(hi);
+    const uint16_t mid = bf16_rne(r1);
+    const float r2 = r1 - bf16_to_f(mid);
+    const uint16_t lo = bf16_rne(r2);
+    uint16_t *dst = a.abf + a.abf_off[s];
+    dst[i] = hi;
+    dst[nbf + i] = mid;
+    dst[2 * nbf + i] = lo;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// point + Gaussian tile kernel
+// ---------------------------------------------------------------------------
+
+template <int PREC>
+struct PgTypes {
+  typedef float acc_t;
+};
+template <>
+struct PgTypes<kFP64> {
+  typedef double acc_t;
+};
+
+template <typename T>
+struct PgSmem {
+  double4 pos[kChunk];
+  double4 gq[kChunk];
+  T flux[kChunk][kPgChan];
+};
+
+// One tile: kTileRows rows x kPgChan channels starting at channel block cb.
+template <int PREC>
+__device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
+                                        PgSmem<typename PgTypes<PREC>::acc_t> &sm) {
+  typedef typename PgTypes<PREC>::acc_t acc_t;
+  constexpr int KB = kPgChan;
+  double4 *s_pos = sm.pos;
+  double4 *s_gq = sm.gq;
+  auto &s_flux = sm.flux;
+  const int k0 = cb * KB;
+  const int tid = threadIdx.x;
+  const int64_t row = (int64_t)rb * kTileRows + tid;
+  const bool valid = row < a.nrows;
+  const int64_t rowc = valid ? row : a.nrows - 1;
+  const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
+
+  double f[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) f[k] = a.fk[k0 + k];
+
+  acc_t sum_re[KB], sum_im[KB], cmp_re[KB], cmp_im[KB], prt_re[KB], prt_im[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) sum_re[k] = sum_im[k] = cmp_re[k] = cmp_im[k] = prt_re[k] = prt_im[k] = 0;
+
+  // FP32-path copies of the row's coordinates
+  const float uf = (float)u, vf = (float)v, wf = (float)w;
+  float ff[KB], f2[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    ff[k] = (float)f[k];
+    f2[k] = (float)(f[k] * f[k]);
+  }
+  const acc_t uu = (acc_t)(u * u), vv = (acc_t)(v * v), uv = (acc_t)(u * v);
+
+  const int J0[2] = {0, a.P};
+  const int JN[2] = {a.P, a.P + a.G};
+#pragma unroll
+  for (int kind = 0; kind < 2; ++kind) {  // 0: points, 1: Gaussians
+    for (int j0 = J0[kind]; j0 < JN[kind]; j0 += kChunk) {
+      const int n = min(kChunk, JN[kind] - j0);
+      __syncthreads();
+      if (tid < n) {
+        s_pos[tid] = a.d.pos[j0 + tid];
+        if (kind == 1) s_gq[tid] = a.d.gq[j0 - a.P + tid];
+      }
+      for (int i = tid; i < n * KB; i += kTileRows) {
+        const int jj = i / KB, k = i % KB;
+        const int64_t fi = (int64_t)(j0 + jj) * a.Kpad + k0 + k;
+        if (PREC == kFP64)
+          s_flux[jj][k] = (acc_t)a.d.flux64[fi];
+        else
+          s_flux[jj][k] = (acc_t)a.d.flux32[fi];
+      }
+      __syncthreads();
+      for (int jj = 0; jj < n; ++jj) {
+        const double4 p = s_pos[jj];
+        acc_t Q = 0;
+        if (kind == 1) {
+          const double4 g = s_gq[jj];
+          if (PREC == kFP64)
+            Q = fma(g.x, u * u, fma(g.y, v * v, g.z * (u * v)));
+          else
+            Q = fmaf((float)g.x, (float)uu, fmaf((float)g.y, (float)vv, (float)g.z * (float)uv));
+        }
+        if (PREC == kFP64) {
+          const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            double c, s;
+            turns_sincos_f64(t0 * f[k], c, s);
+            double S = (double)s_flux[jj][k];
+            if (kind == 1) S *= exp2(-(double)Q * (f[k] * f[k]));
+            prt_re[k] = fma(S, c, (double)prt_re[k]);
+            prt_im[k] = fma(S, s, (double)prt_im[k]);
+          }
+        } else if (PREC == kFP32) {
+          const float t0 = fmaf(uf, (float)p.x, fmaf(vf, (float)p.y, wf * (float)p.z));
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            float c, s;
+            turns_sincos_f32(t0 * ff[k], c, s);
+            float S = (float)s_flux[jj][k];
+            if (kind == 1) S *= __builtin_amdgcn_exp2f(-(float)Q * f2[k]);
+            prt_re[k] = fmaf(S, c, (float)prt_re[k]);
+            prt_im[k] = fmaf(S, s, (float)prt_im[k]);
+          }
+        } else {
+          const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            float c, s;
+            turns_sincos_mixed(t0 * f[k], c, s);
+            float S = (float)s_flux[jj][k];
+            if (kind == 1) S *= __builtin_amdgcn_exp2f(-(float)Q * f2[k]);
+            prt_re[k] = fmaf(S, c, (float)prt_re[k]);
+            prt_im[k] = fmaf(S, s, (float)prt_im[k]);
+          }
+        }
+        if ((jj & (kFlush - 1)) == kFlush - 1 || jj == n - 1) {
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            kahan_add(sum_re[k], cmp_re[k], prt_re[k]);
+            kahan_add(sum_im[k], cmp_im[k], prt_im[k]);
+            prt_re[k] = prt_im[k] = 0;
+          }
+        }
+      }
+    }
+  }
+
+  if (!valid) return;
+  const int64_t base = row * a.K;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (k0 + k >= a.K) break;
+    const int64_t idx = base + k0 + k;
+    if (a.c64) {
+      float re = (float)(sum_re[k] - cmp_re[k]), im = (float)(sum_im[k] - cmp_im[k]);
+      if (a.conj) im = -im;
+      float2 *o = (float2 *)a.vis + idx;
+      if (a.subtract) {
+        const float2 d = *o;
+        *o = make_float2(d.x - re, d.y - im);
+      } else {
+        *o = make_float2(re, im);
+      }
+    } else {
+      double re = (double)sum_re[k] - (double)cmp_re[k], im = (double)sum_im[k] - (double)cmp_im[k];
+      if (a.conj) im = -im;
+      double2 *o = (double2 *)a.vis + idx;
+      if (a.subtract) {
+        const double2 d = *o;
+        *o = make_double2(d.x - re, d.y - im);
+      } else {
+        *o = make_double2(re, im);
+      }
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kTileRows) void k_pg_tile(TileArgs a) {
+  __shared__ PgSmem<typename PgTypes<PREC>::acc_t> sm;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  pg_tile<PREC>(a, tile % a.n_rb, tile / a.n_rb, sm);
+}
+
+// ---------------------------------------------------------------------------
+// shapelet tile on MFMA (mixed and FP32-only paths)
+// ---------------------------------------------------------------------------
+
+// Hermite recurrence step, phi_{n+1} = (sqrt2 x phi_n - sqrt(n) phi_{n-1}) / sqrt(n+1).
+template <typename R>
+__device__ __forceinline__ R herm_step(R sx, R pn, R pm1, int n) {
+  return (R)c_isqn1[n] * fma(sx, pn, -(R)c_sqn[n] * pm1);
+}
+
+template <typename R>
+__device__ __forceinline__ R herm_phi0(R x);
+template <>
+__device__ __forceinline__ double herm_phi0<double>(double x) {
+  return hermite_phi0_mixed(x);
+}
+template <>
+__device__ __forceinline__ float herm_phi0<float>(float x) {
+  return (float)kPiM14 * __builtin_amdgcn_exp2f(-x * x * (float)kHalfLog2e);
+}
+
+// MFMA K steps summed in the FP32 accumulator before the partial n1 sum is
+// folded into the FP64 envelope accumulator.  The signed coefficients cancel
+// heavily (sum |C| is hundreds of times |xi(0)| for the synthetic skies), so
+// an FP32 sum over all orders loses ~1e-6 of the envelope; folding every
+// 2 steps (8 orders) keeps the loss near 4e-7 of total flux on the
+// shapelet-dominated workload.
+constexpr int kFoldSteps = 2;
+
+// ACC: accumulator of the tile's visibilities while shapelets are added
+// (double on the mixed path, float on the FP32-only path).
+template <typename ACC>
+struct ShpSmem {
+  ACC acc_re[kShpChan][kTileRows], acc_im[kShpChan][kTileRows];
+  float A[kA32PerShp];
+  double am[kTileRows], bm[kTileRows], t0[kTileRows];
+};
+
+// Per (visibility, shapelet) start value and phasor.  The synthetic envelopes
+// reach ~15x their value at the uv origin, so on the mixed path these O(1)
+// steps run in FP64 (exp, sincospi, product and sum) to keep their relative
+// error from being magnified against the component's total flux.
+template <typename R>
+__device__ __forceinline__ R shp_phi0(R x);
+template <>
+__device__ __forceinline__ double shp_phi0<double>(double x) {
+  return kPiM14 * exp(-0.5 * x * x);
+}
+template <>
+__device__ __forceinline__ float shp_phi0<float>(float x) {
+  return (float)kPiM14 * __builtin_amdgcn_exp2f(-x * x * (float)kHalfLog2e);
+}
+
+// One tile: kTileRows rows x kShpChan channels starting at channel block cb.
+// Each wave owns 64 rows; a group of 32 visibilities (32 rows of one channel)
+// is the N dimension of the MFMA, lanes l and l + 32 holding the two K
+// halves.  REC is the recurrence type, DOT the envelope accumulator type.
+template <typename REC, typename DOT>
+__device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpSmem<DOT> &sm) {
+  constexpr int KB = kShpChan;
+  const int k0 = cb * KB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, vv = lane & 31;
+  const int64_t row = (int64_t)rb * kTileRows + tid;
+  const bool valid = row < a.nrows;
+  const int64_t rowc = valid ? row : a.nrows - 1;
+  const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
+  const int K = a.K;
+
+  // accumulators start from what the point/Gaussian pass left
+  for (int c = 0; c < KB; ++c) {
+    DOT sr = 0, si = 0;
+    if (valid && k0 + c < K) {
+      const int64_t idx = row * K + k0 + c;
+      if (a.c64) {
+        const float2 x = ((const float2 *)a.vis)[idx];
+        sr = (DOT)x.x;
+        si = (DOT)(a.conj ? -x.y : x.y);
+      } else {
+        const double2 x = ((const double2 *)a.vis)[idx];
+        sr = (DOT)x.x;
+        si = (DOT)(a.conj ? -x.y : x.y);
+      }
+    }
+    sm.acc_re[c][tid] = sr;
+    sm.acc_im[c][tid] = si;
+  }
+
+  const DOT sgn = a.subtract ? -1 : 1;
+  const floatx16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < a.S; ++j) {
+    const int N = a.t.nmax[j];
+    const int MB = (N + 32) / 32, S4 = (N + 4) / 4;
+    __syncthreads();
+    {
+      const float *src = a.t.a32 + a.t.a32_off[j];
+      const int n32 = MB * 2 * S4 * 64;
+      for (int i = tid; i < n32; i += kTileRows) sm.A[i] = src[i];
+      const double *fr = a.d.sframe + 12 * j;
+      sm.am[tid] = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
+      sm.bm[tid] = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
+      sm.t0[tid] = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
+    }
+    __syncthreads();
+    const int jg = a.P + a.G + j;
+    for (int c = 0; c < KB; ++c) {
+      if (k0 + c >= K) break;
+      const double f = a.fk[k0 + c];
+      const DOT S = sizeof(DOT) == 8 ? (DOT)a.d.flux64[(int64_t)jg * a.Kpad + k0 + c]
+                                     : (DOT)a.d.flux32[(int64_t)jg * a.Kpad + k0 + c];
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int rl = wave * 64 + hh * 32 + vv;
+        const REC xa = (REC)sm.am[rl] * (REC)f;
+        const REC xb = (REC)sm.bm[rl] * (REC)f;
+        const REC sxa = (REC)1.41421356237309504880 * xa;
+        const REC sxb = (REC)1.41421356237309504880 * xb;
+        const REC pb0 = shp_phi0<REC>(xb);
+        REC pa_m1 = 0, pa_n = shp_phi0<REC>(xa);
+        DOT xr = 0, xi = 0;
+        for (int mb = 0; mb < MB; ++mb) {
+          // first axis: the 16 rows of this 32-row block held by this lane
+          // (MFMA output row 8 (i/4) + 4 h + i % 4)
+          DOT pa[16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // named registers, not an array: a lane-dependent pick from an
+            // array becomes an indexed scratch access
+            const int n = 32 * mb + 8 * q;
+            const REC r0 = pa_n;
+            const REC r1 = herm_step<REC>(sxa, r0, pa_m1, n);
+            const REC r2 = herm_step<REC>(sxa, r1, r0, n + 1);
+            const REC r3 = herm_step<REC>(sxa, r2, r1, n + 2);
+            const REC r4 = herm_step<REC>(sxa, r3, r2, n + 3);
+            const REC r5 = herm_step<REC>(sxa, r4, r3, n + 4);
+            const REC r6 = herm_step<REC>(sxa, r5, r4, n + 5);
+            const REC r7 = herm_step<REC>(sxa, r6, r5, n + 6);
+            const REC r8 = herm_step<REC>(sxa, r7, r6, n + 7);
+            pa_m1 = r7;
+            pa_n = r8;
+            pa[4 * q + 0] = (DOT)(h ? r4 : r0);
+            pa[4 * q + 1] = (DOT)(h ? r5 : r1);
+            pa[4 * q + 2] = (DOT)(h ? r6 : r2);
+            pa[4 * q + 3] = (DOT)(h ? r7 : r3);
+          }
+          // second axis: recurrence feeding the B operand, K restricted to the
+          // triangle n1 + n2 <= N of this block
+          const int smax = (N - 32 * mb) / 4 + 1;
+          REC pb_m1 = 0, pb_n = pb0;
+          floatx16 De = zero16, Do = zero16;
+          for (int s0 = 0; s0 < smax; s0 += kFoldSteps) {
+#pragma unroll
+            for (int uu = 0; uu < kFoldSteps; ++uu) {
+              const int s4 = s0 + uu;
+              if (s4 < smax) {
+                const int n = 4 * s4;
+                const REC q0 = pb_n;
+                const REC q1 = herm_step<REC>(sxb, q0, pb_m1, n);
+                const REC q2 = herm_step<REC>(sxb, q1, q0, n + 1);
+                const REC q3 = herm_step<REC>(sxb, q2, q1, n + 2);
+                const REC q4 = herm_step<REC>(sxb, q3, q2, n + 3);
+                pb_m1 = q3;
+                pb_n = q4;
+                const float be = (float)(h ? q2 : q0);
+                const float bo = (float)(h ? q3 : q1);
+                const int ie = ((mb * 2 + 0) * S4 + s4) * 64 + lane;
+                const int io = ((mb * 2 + 1) * S4 + s4) * 64 + lane;
+                De = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.A[ie], be, uu == 0 ? zero16 : De, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.A[io], bo, uu == 0 ? zero16 : Do, 0, 0, 0);
+              }
+            }
+            // fold: xi += sum over this lane's rows of phi_n1(a) * T[n1]
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              const DOT te = (DOT)De[i], to = (DOT)Do[i];
+              if ((i & 1) == 0) {
+                xr = fma(pa[i], te, xr);
+                xi = fma(pa[i], to, xi);
+              } else {
+                xr = fma(pa[i], to, xr);
+                xi = fma(pa[i], te, xi);
+              }
+            }
+          }
+        }
+        xr += __shfl_xor(xr, 32);
+        xi += __shfl_xor(xi, 32);
+        // phase, flux and accumulation
+        DOT cs, sn;
+        if (sizeof(DOT) == 8) {
+          double c8, s8;
+          turns_sincos_f64(sm.t0[rl] * f, c8, s8);
+          cs = (DOT)c8;
+          sn = (DOT)s8;
+        } else {
+          float c4, s4;
+          turns_sincos_f32((float)sm.t0[rl] * (float)f, c4, s4);
+          cs = (DOT)c4;
+          sn = (DOT)s4;
+        }
+        const DOT tr = sgn * S * (xr * cs - xi * sn);
+        const DOT ti = sgn * S * (xr * sn + xi * cs);
+        if (h == hh) {
+          sm.acc_re[c][rl] += tr;
+          sm.acc_im[c][rl] += ti;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  for (int c = 0; c < KB; ++c) {
+    if (k0 + c >= K) break;
+    const int64_t idx = row * K + k0 + c;
+    const double re = (double)sm.acc_re[c][tid], im = (double)sm.acc_im[c][tid];
+    if (a.c64)
+      ((float2 *)a.vis)[idx] = make_float2((float)re, (float)(a.conj ? -im : im));
+    else
+      ((double2 *)a.vis)[idx] = make_double2(re, a.conj ? -im : im);
+  }
+}
+
+template <typename REC, typename DOT>
+__global__ __launch_bounds__(kTileRows) void k_shp_mfma(TileArgs a) {
+  __shared__ ShpSmem<DOT> sm;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  shp_tile<REC, DOT>(a, tile % a.n_rb, tile / a.n_rb, sm);
+}
+
+// ---------------------------------------------------------------------------
+// shapelet kernel, FP64 path (vector ALU)
+// ---------------------------------------------------------------------------
+
+// One thread per (row, channel) visibility of the tile; the second axis's
+// Hermite values live in registers (NB + 1 of them, NB the order bucket), the
+// first axis's recurrence advances with the n1 loop, and each n1 row of the
+// signed coefficient matrix is read as wave-uniform loads.
+template <int NB>
+__global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
+  constexpr int KB = kShpChan;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int cb = tile / a.n_rb, rb = tile % a.n_rb;
+  const int k0 = cb * KB;
+  const int tid = threadIdx.x;
+  const int64_t row = (int64_t)rb * kTileRows + tid;
+  const bool valid = row < a.nrows;
+  const int64_t rowc = valid ? row : a.nrows - 1;
+  const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
+
+  for (int c = 0; c < KB; ++c) {
+    if (k0 + c >= a.K) break;
+    const double f = a.fk[k0 + c];
+    double acc_re = 0.0, acc_im = 0.0;
+    for (int j = 0; j < a.S; ++j) {
+      const int N = a.t.nmax[j];
+      const double *fr = a.d.sframe + 12 * j;
+      const double xa = f * fma(fr[0], u, fma(fr[1], v, fr[2] * w));
+      const double xb = f * fma(fr[3], u, fma(fr[4], v, fr[5] * w));
+      const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
+      double pb[NB + 8];
+      {
+        const double sx = 1.41421356237309504880 * xb;
+        pb[0] = kPiM14 * exp(-0.5 * xb * xb);
+        double pm1 = 0.0;
+#pragma unroll
+        for (int n = 0; n < NB + 7; ++n) {
+          const double nx = herm_step<double>(sx, pb[n], pm1, n);
+          pm1 = pb[n];
+          pb[n + 1] = nx;
+        }
+      }
+      const double *C = a.t.c64 + a.t.c64_off[j];
+      const int ld = a.t.c64_ld[j];
+      const double sx = 1.41421356237309504880 * xa;
+      double pa = kPiM14 * exp(-0.5 * xa * xa), pam1 = 0.0;
+      double xr = 0.0, xi = 0.0;
+      for (int n1 = 0; n1 <= N; ++n1) {
+        const double *Cr = C + (int64_t)n1 * ld;
+        double te = 0.0, to = 0.0;
+#pragma unroll
+        for (int b8 = 0; b8 < (NB + 8) / 8; ++b8) {
+          if (8 * b8 <= N - n1) {
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+              te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
+              to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
+            }
+          }
+        }
+        if (n1 & 1) {
+          xr = fma(pa, to, xr);
+          xi = fma(pa, te, xi);
+        } else {
+          xr = fma(pa, te, xr);
+          xi = fma(pa, to, xi);
+        }
+        const double nx = herm_step<double>(sx, pa, pam1, n1);
+        pam1 = pa;
+        pa = nx;
+      }
+      double cs, sn;
+      turns_sincos_f64(t0 * f, cs, sn);
+      const double S = a.d.flux64[(int64_t)(a.P + a.G + j) * a.Kpad + k0 + c];
+      acc_re += S * (xr * cs - xi * sn);
+      acc_im += S * (xr * sn + xi * cs);
+    }
+    if (valid) {
+      const int64_t idx = row * a.K + k0 + c;
+      double2 *o = (double2 *)a.vis;
+      float2 *o32 = (float2 *)a.vis;
+      double xr, xi;
+      if (a.c64) {
+        const float2 x = o32[idx];
+        xr = x.x;
+        xi = a.conj ? -x.y : x.y;
+      } else {
+        const double2 x = o[idx];
+        xr = x.x;
+        xi = a.conj ? -x.y : x.y;
+      }
+      if (a.subtract) {
+        xr -= acc_re;
+        xi -= acc_im;
+      } else {
+        xr += acc_re;
+        xi += acc_im;
+      }
+      if (a.conj) xi = -xi;
+      if (a.c64)
+        o32[idx] = make_float2((float)xr, (float)xi);
+      else
+        o[idx] = make_double2(xr, xi);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static hipError_t upload_tables() {
+  static bool done[64] = {false};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
+  double sq[128], isq[128];
+  for (int n = 0; n < 128; ++n) {
+    sq[n] = sqrt((double)n);
+    isq[n] = 1.0 / sqrt((double)n + 1.0);
+  }
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_sqn), sq, sizeof(sq));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_isqn1), isq, sizeof(isq));
+  if (e == hipSuccess && dev >= 0 && dev < 64) done[dev] = true;
+  return e;
+}
+
+hipError_t launch_derive(const DeriveArgs &a, hipStream_t s) {
+  const int J = a.P + a.G + a.S;
+  if (J == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_derive, dim3((J + 127) / 128), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux(const FluxArgs &a, hipStream_t s) {
+  const int64_t n = (int64_t)a.J * a.Kpad;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flux, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles_build(const TileBuildArgs &a, int max_nmax, hipStream_t s) {
+  (void)max_nmax;
+  if (a.S == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tiles, dim3(16, a.S), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pg(const TileArgs &a, int prec, hipStream_t s) {
+  hipError_t e = upload_tables();
+  if (e != hipSuccess) return e;
+  const int64_t nt = (int64_t)a.n_rb * a.n_cb;
+  if (nt <= 0) return hipSuccess;
+  if (nt > 0x7fffffff) return hipErrorInvalidValue;
+  switch (prec) {
+    case kFP64:
+      hipLaunchKernelGGL(k_pg_tile<kFP64>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+      break;
+    case kFP32:
+      hipLaunchKernelGGL(k_pg_tile<kFP32>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(k_pg_tile<kMixed>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) {
+  hipError_t e = upload_tables();
+  if (e != hipSuccess) return e;
+  const int64_t nt = (int64_t)a.n_rb * a.n_cb;
+  if (nt <= 0 || a.S == 0) return hipSuccess;
+  if (nt > 0x7fffffff) return hipErrorInvalidValue;
+  if (max_nmax < 0 || max_nmax > kNmaxLimit) return hipErrorInvalidValue;
+  const dim3 g((unsigned)nt), b(kTileRows);
+  switch (prec) {
+    case kFP64:
+      if (max_nmax <= 16)
+        hipLaunchKernelGGL(k_shp_fp64<16>, g, b, 0, s, a);
+      else if (max_nmax <= 32)
+        hipLaunchKernelGGL(k_shp_fp64<32>, g, b, 0, s, a);
+      else if (max_nmax <= 64)
+        hipLaunchKernelGGL(k_shp_fp64<64>, g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL(k_shp_fp64<96>, g, b, 0, s, a);
+      break;
+    case kFP32:
+      hipLaunchKernelGGL((k_shp_mfma<float, float>), g, b, 0, s, a);
+      break;
+    case kMixed:
+      hipLaunchKernelGGL((k_shp_mfma<double, double>), g, b, 0, s, a);
+      break;
+    default:
+      return hipErrorNotSupported;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vp

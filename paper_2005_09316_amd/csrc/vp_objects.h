@@ -1,0 +1,119 @@
+// vp_objects.h -- host-side objects behind the opaque handles of vp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <set>
+#include <utility>
+#include <vector>
+
+#include "vp_internal.h"
+
+struct vp_ctx;
+
+namespace vp {
+
+struct Scheduler;
+
+// Device allocations owned by one object; released together.
+struct DeviceMem {
+  std::vector<void *> ptrs;
+  size_t total = 0;
+  hipError_t alloc(void **p, size_t bytes);
+  void release();
+};
+
+struct DerivedEntry {
+  Derived d;
+  DeviceMem mem;
+  hipEvent_t ready = nullptr;  // recorded after the tables are built
+  hipStream_t ready_stream = nullptr;
+};
+
+struct ProfRecord {
+  int kind;
+  hipEvent_t e0, e1;
+};
+
+// Records a pair of events around the kernels launched in its lifetime when
+// profiling is enabled on the context.
+struct ProfScope {
+  vp_ctx *ctx;
+  hipStream_t stream;
+  int kind;
+  bool active = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(vp_ctx *c, hipStream_t s, int k);
+  void end();
+  ~ProfScope();
+};
+
+// Selects a HIP device for the lifetime of the guard, restoring the previous one.
+struct DeviceGuard {
+  int prev = 0;
+  bool ok = false;
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+};
+
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+int run_tiles(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs *obs, int precision, int dtype,
+              void *vis, int subtract, hipStream_t stream);
+int check_call(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs *obs, int precision, int dtype,
+               void *vis);
+void drop_derived(vp_ctx *ctx, uint64_t sky_id, uint64_t obs_id);
+void drop_all_derived(vp_ctx *ctx);
+
+// serving hooks (vp_serve.cpp)
+bool serve_pending(vp_ctx *ctx);
+void serve_shutdown(vp_ctx *ctx);
+
+}  // namespace vp
+
+struct vp_obs {
+  vp_ctx *ctx = nullptr;
+  uint64_t id = 0;
+  int T = 0, B = 0, K = 0, Kpad = 0;
+  double ra0 = 0, dec0 = 0;
+  int sign = -1;
+  double beam_fwhm = 0, beam_nu_ref = 0;
+  double *uvw = nullptr;  // device [T*B][3]
+  double *freq = nullptr; // device [K]
+  double *fk = nullptr;   // device [Kpad], nu/c
+  std::vector<double> h_freq;
+  int jobs = 0;           // pending serving jobs using it (guarded by ctx->mu)
+  vp::DeviceMem mem;
+};
+
+struct vp_sky {
+  vp_ctx *ctx = nullptr;
+  uint64_t id = 0;
+  int P = 0, G = 0, S = 0;
+  double nu_ref = 0;
+  int max_nmax = 0;
+  std::vector<int32_t> h_nmax;
+  double *ra = nullptr, *dec = nullptr, *sref = nullptr, *alpha = nullptr;  // device [J]
+  double *g_maj = nullptr, *g_min = nullptr, *g_pa = nullptr;               // device [G]
+  double *s_beta1 = nullptr, *s_beta2 = nullptr, *s_pa = nullptr;          // device [S]
+  vp::ShpTiles tiles;
+  int jobs = 0;
+  vp::DeviceMem mem;
+};
+
+struct vp_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  std::mutex mu;  // guards the object sets, the derived cache and job counts
+  uint64_t next_id = 0;
+  std::set<vp_obs *> obs;
+  std::set<vp_sky *> skies;
+  std::map<std::pair<uint64_t, uint64_t>, vp::DerivedEntry *> derived;
+  uint64_t lib_bytes = 0;
+  bool profile = false;
+  std::mutex prof_mu;
+  std::vector<vp::ProfRecord> prof_pending;
+  vp::Scheduler *sched = nullptr;
+};

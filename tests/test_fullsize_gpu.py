@@ -1,0 +1,107 @@
+"""Full-size workloads on the GPU, checked against the oracle on sampled rows.
+
+The GPU computes every visibility of the workload in the launch configuration
+the benchmark times; the oracle evaluates a seeded sample of (time, baseline)
+rows, all channels, all components, and the error metric is taken over the
+sample.  Peel: resident complex64 data (seeded noise, so that no input comes
+from the GPU path) has the bright shapelets subtracted one after another."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2005_09316_amd import vp
+from tests.helpers import Handles
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = vp.vp_create_ctx(0, 0)
+    yield c
+    vp.vp_destroy_ctx(c)
+
+
+def _predict_rows(ctx, obs, sky, prec, dtype, rows):
+    import torch
+    tdt = torch.complex64 if dtype == vp.VP_C64 else torch.complex128
+    out = torch.empty((obs.n_time * obs.n_bl, obs.n_chan), dtype=tdt, device="cuda")
+    s = torch.cuda.current_stream()
+    with Handles(ctx, obs, sky) as h:
+        t0 = time.time()
+        vp.vp_predict(ctx, h.sky, h.obs, prec, dtype, out.data_ptr(), s.cuda_stream)
+        s.synchronize()
+        dt = time.time() - t0
+    got = out[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.complex128)
+    assert bool(torch.isfinite(torch.view_as_real(out)).all())
+    return got, dt
+
+
+@pytest.mark.parametrize("cfg,nrows_sample", [(1, 192), (2, 384)])
+@pytest.mark.parametrize("prec,dtype,tol", [(vp.VP_PREC_MIXED, vp.VP_C64, 1e-6),
+                                            (vp.VP_PREC_MIXED, vp.VP_C128, 1e-6),
+                                            (vp.VP_PREC_FP64, vp.VP_C128, 1e-11)])
+def test_fullsize_sampled(ctx, cfg, nrows_sample, prec, dtype, tol):
+    obs, sky = synth.make_config(cfg)
+    rows = np.sort(np.random.default_rng(100 + cfg).choice(obs.n_time * obs.n_bl, nrows_sample, replace=False))
+    _log("workload %d: %d vis, precision %d, dtype %d" % (cfg, obs.n_vis, prec, dtype))
+    got, dt = _predict_rows(ctx, obs, sky, prec, dtype, rows)
+    ref = oracle.predict(obs, sky, rows=rows)
+    err = oracle.error_metric(got, ref, obs, sky)
+    _log("  gpu %.1f ms (first call, with table build); sampled error / total flux = %.3e" % (dt * 1e3, err))
+    assert err <= tol
+
+
+def test_large_peel_sampled(ctx):
+    """Workload 4: 12.5M visibilities; subtract the 10 bright shapelets one at
+    a time from resident complex64 data, on the mixed path, then compare the
+    residual on sampled rows with D - sum_k V_k from the oracle."""
+    import torch
+    obs, sky = synth.make_config(4)
+    nrows = obs.n_time * obs.n_bl
+    rows = np.sort(np.random.default_rng(404).choice(nrows, 24, replace=False))
+    data = synth.noise_c64((nrows, obs.n_chan), seed=404)
+    d_dev = torch.from_numpy(data).to("cuda")
+    s = torch.cuda.current_stream()
+    oh = vp.vp_create_obs(ctx, obs)
+    peel = [synth.select_components(sky, points=[], gauss=[], shapelets=[k]) for k in range(sky.n_shp)]
+    handles = [vp.vp_create_sky(ctx, p) for p in peel]
+    t0 = time.time()
+    for h in handles:
+        vp.vp_subtract(ctx, h, oh, vp.VP_PREC_MIXED, vp.VP_C64, d_dev.data_ptr(), s.cuda_stream)
+    s.synchronize()
+    _log("10 peel subtractions: %.1f ms (first calls, with table builds)" % ((time.time() - t0) * 1e3))
+    got = d_dev[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.complex128)
+    shp_sky = synth.select_components(sky, points=[], gauss=[], shapelets=None)
+    ref = data[rows].astype(np.complex128) - oracle.predict(obs, shp_sky, rows=rows)
+    err = oracle.error_metric(got, ref, obs, shp_sky)
+    rms_res = np.sqrt(np.mean(np.abs(got - ref) ** 2))
+    _log("  peel residual: sampled error / total shapelet flux = %.3e, rms(R_gpu - R_ref) = %.3e Jy, "
+         "rms(R_ref) = %.3e Jy" % (err, rms_res, np.sqrt(np.mean(np.abs(ref) ** 2))))
+    for h in handles:
+        vp.vp_destroy_sky(h)
+    vp.vp_destroy_obs(oh)
+    # complex64 data of ~1 Jy noise: its own rounding is ~6e-8 Jy; the bar is
+    # the mixed-path bar relative to the peeled flux
+    assert err <= 1e-6
+
+
+def test_large_full_sky_sampled(ctx):
+    """Workload 4's full sky (100000 points, 5000 Gaussians, 10 shapelets)
+    predicted on the mixed path, sampled rows against the oracle."""
+    obs, sky = synth.make_config(4)
+    rows = np.sort(np.random.default_rng(405).choice(obs.n_time * obs.n_bl, 6, replace=False))
+    got, dt = _predict_rows(ctx, obs, sky, vp.VP_PREC_MIXED, vp.VP_C64, rows)
+    ref = oracle.predict(obs, sky, rows=rows)
+    err = oracle.error_metric(got, ref, obs, sky)
+    _log("workload 4 full sky: gpu %.1f ms (first call); sampled error / total flux = %.3e" % (dt * 1e3, err))
+    assert err <= 1e-6

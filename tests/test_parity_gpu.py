@@ -1,0 +1,182 @@
+"""GPU parity: libvp's HIP kernels against the FP64 oracle, element by element,
+on seeded synthetic inputs.
+
+Error metric: max over channels of max |V_gpu - V_oracle| / F_k, F_k the total
+flux of channel k (sum of |S_j(nu_k)| |xi_j(0)|).  Bars: 1e-11 for the FP64
+path, 1e-6 for the mixed paths (FP64 phase, FP32 sincos/envelopes/MFMA
+contraction, Kahan sums).  The FP32-only path is reported, not gated.
+
+Sizes here span several 256-row tiles with ragged row and channel tails; the
+full-size workloads are checked on sampled rows in test_fullsize_gpu.py."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2005_09316_amd import vp
+from tests.helpers import Handles, run
+
+pytestmark = pytest.mark.gpu
+
+TOL = {vp.VP_PREC_FP64: 1e-11, vp.VP_PREC_MIXED: 1e-6}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = vp.vp_create_ctx(0, 0)
+    yield c
+    vp.vp_destroy_ctx(c)
+
+
+def _case(name):
+    if name == "tiny":
+        return synth.make_config(0)
+    if name == "mwa-mid":
+        # 24 tiles (276 baselines) x 3 times = 828 rows: 4 row tiles, ragged;
+        # 13 channels: ragged against 8- and 4-channel blocks; beam on.
+        return synth.make_config(1, n_tiles=24, n_time=3, n_chan=13, n_point=300, n_gauss=60,
+                                 shapelet_nmax=[54, 33])
+    if name == "fornax-mid":
+        return synth.make_config(2, n_tiles=20, n_time=2, n_chan=6)
+    if name == "nmax-limit":
+        return synth.make_config(0, n_tiles=16, n_time=2, n_chan=5, n_point=3, n_gauss=2,
+                                 shapelet_nmax=[96, 0, 1, 31, 32, 63, 64])
+    raise KeyError(name)
+
+
+CASES = ["tiny", "mwa-mid", "fornax-mid", "nmax-limit"]
+_REF = {}
+
+
+def _ref(name):
+    if name not in _REF:
+        obs, sky = _case(name)
+        _REF[name] = (obs, sky, oracle.predict(obs, sky))
+    return _REF[name]
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec,dtype", [(vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C128),
+                                        (vp.VP_PREC_MIXED, vp.VP_C64)])
+def test_predict_matches_oracle(ctx, name, prec, dtype):
+    obs, sky, ref = _ref(name)
+    _log("case", name, "prec", prec, "dtype", dtype, "vis", obs.n_vis)
+    with Handles(ctx, obs, sky) as h:
+        got = run(ctx, h.obs, h.sky, obs, prec, dtype)
+    err = oracle.error_metric(got, ref, obs, sky)
+    _log("  error / total flux = %.3e" % err)
+    tol = TOL[prec]
+    if dtype == vp.VP_C64:
+        tol = max(tol, 1e-6)
+    assert np.all(np.isfinite(got))
+    assert err <= tol
+
+
+@pytest.mark.parametrize("name", ["tiny", "fornax-mid"])
+def test_fp32_only_path_is_reported(ctx, name):
+    obs, sky, ref = _ref(name)
+    with Handles(ctx, obs, sky) as h:
+        got = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_FP32, vp.VP_C64)
+    err = oracle.error_metric(got, ref, obs, sky)
+    _log("FP32-only path, case %s: error / total flux = %.3e (not gated)" % (name, err))
+    assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("prec,dtype", [(vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C64)])
+def test_subtract_matches_oracle_residual(ctx, prec, dtype):
+    obs, sky, ref = _ref("mwa-mid")
+    rng = np.random.default_rng(17)
+    data = ref + (rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape))
+    if dtype == vp.VP_C64:
+        data = data.astype(np.complex64).astype(np.complex128)
+    with Handles(ctx, obs, sky) as h:
+        got = run(ctx, h.obs, h.sky, obs, prec, dtype, data=data)
+    err = oracle.error_metric(got, data - ref, obs, sky)
+    _log("subtract prec %d: error / total flux = %.3e" % (prec, err))
+    assert err <= TOL[prec] if dtype == vp.VP_C128 else err <= 1e-6
+
+
+def test_sign_flip_is_exact_conjugate(ctx):
+    obs, sky, _ = _ref("mwa-mid")
+    plus = synth.Obs(**{**obs.__dict__, "sign": +1})
+    for prec in (vp.VP_PREC_FP64, vp.VP_PREC_MIXED):
+        with Handles(ctx, obs, sky) as h, Handles(ctx, plus, sky) as hp:
+            a = run(ctx, h.obs, h.sky, obs, prec, vp.VP_C128)
+            b = run(ctx, hp.obs, hp.sky, plus, prec, vp.VP_C128)
+        assert np.array_equal(a, np.conj(b))
+
+
+def test_deterministic_bitwise(ctx):
+    obs, sky, _ = _ref("fornax-mid")
+    with Handles(ctx, obs, sky) as h:
+        a = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_MIXED, vp.VP_C64)
+        b = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_MIXED, vp.VP_C64)
+    assert np.array_equal(a, b)
+
+
+def test_subtract_of_predict_is_zero_and_linearity(ctx):
+    obs, sky, _ = _ref("mwa-mid")
+    a = synth.select_components(sky, points=range(0, 150), gauss=range(0, 30), shapelets=[0])
+    b = synth.select_components(sky, points=range(150, 300), gauss=range(30, 60), shapelets=[1])
+    with Handles(ctx, obs, sky) as h, Handles(ctx, obs, a) as ha, Handles(ctx, obs, b) as hb:
+        full = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_FP64, vp.VP_C128)
+        va = run(ctx, ha.obs, ha.sky, obs, vp.VP_PREC_FP64, vp.VP_C128)
+        vb = run(ctx, hb.obs, hb.sky, obs, vp.VP_PREC_FP64, vp.VP_C128)
+        zero = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_FP64, vp.VP_C128, data=full)
+    F = oracle.total_flux(obs, sky)
+    assert np.max(np.abs(zero) / F) < 1e-13
+    assert oracle.error_metric(va + vb, full, obs, sky) < 1e-12
+
+
+def test_empty_sky_and_edge_shapes(ctx):
+    obs, sky = synth.make_config(0, n_tiles=3, n_time=1, n_chan=1)
+    empty = synth.empty_sky()
+    for prec in (vp.VP_PREC_FP64, vp.VP_PREC_MIXED):
+        with Handles(ctx, obs, empty) as h:
+            z = run(ctx, h.obs, h.sky, obs, prec, vp.VP_C128)
+            assert np.all(z == 0)
+            d = np.arange(obs.n_vis).reshape(1, obs.n_bl, 1) * (1 + 2j)
+            same = run(ctx, h.obs, h.sky, obs, prec, vp.VP_C128, data=d)
+            assert np.array_equal(same, d)
+    # one row, one channel, each component kind alone
+    for sel in ({"points": [0], "gauss": [], "shapelets": []}, {"points": [], "gauss": [0], "shapelets": []},
+                {"points": [], "gauss": [], "shapelets": [0]}):
+        s = synth.select_components(sky, **sel)
+        one = synth.Obs(**{**obs.__dict__, "n_bl": 1, "uvw_m": obs.uvw_m[:, :1]})
+        ref = oracle.predict(one, s)
+        for prec in (vp.VP_PREC_FP64, vp.VP_PREC_MIXED):
+            with Handles(ctx, one, s) as h:
+                got = run(ctx, h.obs, h.sky, one, prec, vp.VP_C128)
+            assert oracle.error_metric(got, ref, one, s) <= TOL[prec]
+
+
+def test_invalid_inputs_rejected(ctx):
+    obs, sky = synth.make_config(0, n_tiles=4)
+    bad = synth.Obs(**{**obs.__dict__, "sign": 2})
+    with pytest.raises(vp.VPError) as e:
+        vp.vp_create_obs(ctx, bad)
+    assert e.value.code == vp.VP_EINVAL
+    nan = synth.Obs(**{**obs.__dict__, "uvw_m": obs.uvw_m * np.nan})
+    with pytest.raises(vp.VPError):
+        vp.vp_create_obs(ctx, nan)
+    s2 = synth.select_components(sky)
+    s2.s_nmax = np.array([97], np.int32)
+    with pytest.raises(vp.VPError):
+        vp.vp_create_sky(ctx, s2)
+    s3 = synth.select_components(sky)
+    s3.s_beta1 = np.array([0.0])
+    with pytest.raises(vp.VPError):
+        vp.vp_create_sky(ctx, s3)
+    with Handles(ctx, obs, sky) as h:
+        with pytest.raises(vp.VPError):
+            vp.vp_predict(ctx, h.sky, h.obs, 7, vp.VP_C64, 1234, 0)
+        with pytest.raises(vp.VPError):
+            vp.vp_predict(ctx, h.sky, h.obs, vp.VP_PREC_MIXED, 5, 1234, 0)
