@@ -167,7 +167,10 @@ typedef struct {
   uint64_t t_submit, t_admit, t_start, t_done; /* CLOCK_MONOTONIC ns */
 } vp_job_result;
 
-/* Enqueue a job; returns a ticket.  The job is admitted when its HBM footprint
+/* Enqueue a job; returns a ticket.  The caller's writes to job->vis_dev (the
+ * data of a subtract job) must be complete, i.e. the writing stream
+ * synchronised, before the call.  Only VP_PREC_MIXED is served.  The job is
+ * admitted when its HBM footprint
  * fits the budget minus what admitted jobs hold, in FIFO order; admitted jobs
  * are expanded into tiles that a persistent device kernel processes together
  * with the tiles of other admitted jobs.  Errors: VP_EINVAL, VP_ECAPACITY if

@@ -8,8 +8,10 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <chrono>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -76,70 +78,128 @@ void DeviceMem::release() {
 // derived (sky, obs) tables
 // ---------------------------------------------------------------------------
 
-static int build_derived(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, hipStream_t stream,
-                         DerivedEntry **out) {
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  auto key = std::make_pair(sky->id, obs->id);
-  auto it = ctx->derived.find(key);
-  if (it != ctx->derived.end()) {
-    DerivedEntry *d = it->second;
-    if (d->ready_stream != stream) {
-      hipError_t e = hipStreamWaitEvent(stream, d->ready, 0);
-      if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
-    }
-    *out = d;
-    return VP_OK;
-  }
+static int alloc_derived(const vp_sky *sky, const vp_obs *obs, DerivedEntry **out) {
   DerivedEntry *d = new DerivedEntry();
   const int J = sky->P + sky->G + sky->S;
-  hipError_t e = hipSuccess;
   const int Jc = std::max(J, 1), Gc = std::max(sky->G, 1), Sc = std::max(sky->S, 1);
-  if (e == hipSuccess) e = d->mem.alloc((void **)&d->d.pos, sizeof(double4) * Jc);
+  hipError_t e = d->mem.alloc((void **)&d->d.pos, sizeof(double4) * Jc);
   if (e == hipSuccess) e = d->mem.alloc((void **)&d->d.gq, sizeof(double4) * Gc);
   if (e == hipSuccess) e = d->mem.alloc((void **)&d->d.sframe, sizeof(double) * 12 * Sc);
   if (e == hipSuccess) e = d->mem.alloc((void **)&d->d.flux32, sizeof(float) * (size_t)Jc * obs->Kpad);
   if (e == hipSuccess) e = d->mem.alloc((void **)&d->d.flux64, sizeof(double) * (size_t)Jc * obs->Kpad);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&d->ready, hipEventDisableTiming);
   if (e != hipSuccess) {
     d->mem.release();
     delete d;
     return hip_error(e, "allocating per-(sky, observation) tables");
   }
+  *out = d;
+  return VP_OK;
+}
+
+DeriveArgs make_derive_args(const vp_sky *sky, const vp_obs *obs, const Derived &d) {
   DeriveArgs da;
   da.P = sky->P; da.G = sky->G; da.S = sky->S;
   da.ra = sky->ra; da.dec = sky->dec;
   da.g_maj = sky->g_maj; da.g_min = sky->g_min; da.g_pa = sky->g_pa;
   da.s_beta1 = sky->s_beta1; da.s_beta2 = sky->s_beta2; da.s_pa = sky->s_pa;
   da.ra0 = obs->ra0; da.dec0 = obs->dec0;
-  da.d = d->d;
+  da.d = d;
+  return da;
+}
+
+FluxArgs make_flux_args(const vp_sky *sky, const vp_obs *obs, const Derived &d) {
   FluxArgs fa;
-  fa.J = J; fa.K = obs->K; fa.Kpad = obs->Kpad;
-  fa.sref = sky->sref; fa.alpha = sky->alpha; fa.freq = obs->freq;
-  fa.nu_ref = sky->nu_ref; fa.beam_fwhm = obs->beam_fwhm; fa.beam_nu_ref = obs->beam_nu_ref;
-  fa.d = d->d;
-  ProfScope ps(ctx, stream, 0);
-  e = launch_derive(da, stream);
-  if (e == hipSuccess) e = launch_flux(fa, stream);
-  ps.end();
-  if (e == hipSuccess) e = hipEventRecord(d->ready, stream);
-  if (e != hipSuccess) {
-    d->mem.release();
-    delete d;
-    return hip_error(e, "building per-(sky, observation) tables");
+  fa.J = sky->P + sky->G + sky->S; fa.K = obs->K; fa.Kpad = obs->Kpad;
+  fa.sref = sky->sref; fa.alpha = sky->alpha; fa.ra = sky->ra; fa.dec = sky->dec; fa.freq = obs->freq;
+  fa.nu_ref = sky->nu_ref; fa.ra0 = obs->ra0; fa.dec0 = obs->dec0;
+  fa.beam_fwhm = obs->beam_fwhm; fa.beam_nu_ref = obs->beam_nu_ref;
+  fa.d = d;
+  return fa;
+}
+
+int get_derived(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, hipStream_t stream, DerivedEntry **out) {
+  const auto key = std::make_pair(sky->id, obs->id);
+  for (;;) {
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    auto it = ctx->derived.find(key);
+    if (it != ctx->derived.end()) {
+      DerivedEntry *d = it->second;
+      if (d->building) {  // being built by the serving kernel
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+        continue;
+      }
+      if (d->ready && d->ready_stream != stream) {
+        hipError_t e = hipStreamWaitEvent(stream, d->ready, 0);
+        if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
+      }
+      *out = d;
+      return VP_OK;
+    }
+    DerivedEntry *d = nullptr;
+    int rc = alloc_derived(sky, obs, &d);
+    if (rc != VP_OK) return rc;
+    hipError_t e = hipEventCreateWithFlags(&d->ready, hipEventDisableTiming);
+    if (e == hipSuccess) {
+      ProfScope ps(ctx, stream, 0);
+      e = launch_derive(make_derive_args(sky, obs, d->d), stream);
+      if (e == hipSuccess) e = launch_flux(make_flux_args(sky, obs, d->d), stream);
+      ps.end();
+    }
+    if (e == hipSuccess) e = hipEventRecord(d->ready, stream);
+    if (e != hipSuccess) {
+      if (d->ready) (void)hipEventDestroy(d->ready);
+      d->mem.release();
+      delete d;
+      return hip_error(e, "building per-(sky, observation) tables");
+    }
+    d->ready_stream = stream;
+    ctx->derived[key] = d;
+    ctx->lib_bytes += d->mem.total;
+    *out = d;
+    return VP_OK;
   }
-  d->ready_stream = stream;
+}
+
+int serve_derived(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, DerivedEntry **out, bool *build) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const auto key = std::make_pair(sky->id, obs->id);
+  auto it = ctx->derived.find(key);
+  if (it != ctx->derived.end()) {
+    *out = it->second;
+    *build = false;
+    return VP_OK;
+  }
+  DerivedEntry *d = nullptr;
+  int rc = alloc_derived(sky, obs, &d);
+  if (rc != VP_OK) return rc;
+  d->building = true;
   ctx->derived[key] = d;
   ctx->lib_bytes += d->mem.total;
   *out = d;
+  *build = true;
   return VP_OK;
+}
+
+bool derived_ready(vp_ctx *ctx, DerivedEntry *d) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (d->building) return false;
+  return !d->ready || hipEventQuery(d->ready) == hipSuccess;
+}
+
+void derived_built(vp_ctx *ctx, DerivedEntry *d) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  d->building = false;
 }
 
 void drop_derived(vp_ctx *ctx, uint64_t sky_id, uint64_t obs_id) {
   // caller holds ctx->mu; an id of 0 matches nothing
   for (auto it = ctx->derived.begin(); it != ctx->derived.end();) {
     if ((sky_id && it->first.first == sky_id) || (obs_id && it->first.second == obs_id)) {
-      (void)hipEventSynchronize(it->second->ready);
-      (void)hipEventDestroy(it->second->ready);
+      if (it->second->ready) {
+        (void)hipEventSynchronize(it->second->ready);
+        (void)hipEventDestroy(it->second->ready);
+      }
       ctx->lib_bytes -= it->second->mem.total;
       it->second->mem.release();
       delete it->second;
@@ -153,8 +213,10 @@ void drop_derived(vp_ctx *ctx, uint64_t sky_id, uint64_t obs_id) {
 void drop_all_derived(vp_ctx *ctx) {
   // caller holds ctx->mu
   for (auto &kv : ctx->derived) {
-    (void)hipEventSynchronize(kv.second->ready);
-    (void)hipEventDestroy(kv.second->ready);
+    if (kv.second->ready) {
+      (void)hipEventSynchronize(kv.second->ready);
+      (void)hipEventDestroy(kv.second->ready);
+    }
     ctx->lib_bytes -= kv.second->mem.total;
     kv.second->mem.release();
     delete kv.second;
@@ -195,7 +257,7 @@ ProfScope::~ProfScope() { end(); }
 int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis,
               int subtract, hipStream_t stream) {
   DerivedEntry *d = nullptr;
-  int rc = build_derived(ctx, sky, obs, stream, &d);
+  int rc = get_derived(ctx, sky, obs, stream, &d);
   if (rc != VP_OK) return rc;
   TileArgs a;
   a.nrows = (int64_t)obs->T * obs->B;

@@ -24,25 +24,26 @@ constexpr int kBf16Chunks = 4;  // 16-wide K steps of one parity: ceil(49 / 16)
 
 enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4 };
 
-// Per-(sky, observation) tables, built on the device.
+// Per-(sky, observation) tables, built on the device.  Plain aggregates (no
+// member initialisers) so that they can live in LDS inside the serving kernel.
 struct Derived {
-  double4 *pos = nullptr;   // [J] (l, m, n-1, 0), components in order points, Gaussians, shapelets
-  double4 *gq = nullptr;    // [G] quadratic form of the Gaussian envelope exponent (base 2), metres^2
-  double *sframe = nullptr; // [S][12] a-vector(3), b-vector(3), (l, m, n-1)(3), pad(3)
-  float *flux32 = nullptr;  // [J][Kpad]
-  double *flux64 = nullptr; // [J][Kpad]
+  double4 *pos;   // [J] (l, m, n-1, 0), components in order points, Gaussians, shapelets
+  double4 *gq;    // [G] quadratic form of the Gaussian envelope exponent (base 2), metres^2
+  double *sframe; // [S][12] a-vector(3), b-vector(3), (l, m, n-1)(3), pad(3)
+  float *flux32;  // [J][Kpad]
+  double *flux64; // [J][Kpad]
 };
 
 // Shapelet coefficient tiles (depend on the sky only).
 struct ShpTiles {
-  const float *a32 = nullptr;        // MFMA A-operand tiles, FP32
-  const int64_t *a32_off = nullptr;  // [S]
-  const double *c64 = nullptr;       // dense signed coefficients [n1][ld], FP64
-  const int64_t *c64_off = nullptr;  // [S]
-  const int32_t *c64_ld = nullptr;   // [S] leading dimension (multiple of 8)
-  const uint16_t *abf = nullptr;     // BF16 split A tiles: [part][mb][par][chunk][64][8]
-  const int64_t *abf_off = nullptr;  // [S]
-  const int32_t *nmax = nullptr;     // [S]
+  const float *a32;        // MFMA A-operand tiles, FP32
+  const int64_t *a32_off;  // [S]
+  const double *c64;       // dense signed coefficients [n1][ld], FP64
+  const int64_t *c64_off;  // [S]
+  const int32_t *c64_ld;   // [S] leading dimension (multiple of 8)
+  const uint16_t *abf;     // BF16 split A tiles: [part][mb][par][chunk][64][8]
+  const int64_t *abf_off;  // [S]
+  const int32_t *nmax;     // [S]
 };
 
 struct DeriveArgs {
@@ -57,8 +58,10 @@ struct DeriveArgs {
 struct FluxArgs {
   int J, K, Kpad;
   const double *sref, *alpha;  // [J]
+  const double *ra, *dec;      // [J], for the beam
   const double *freq;          // [K]
   double nu_ref;
+  double ra0, dec0;
   double beam_fwhm, beam_nu_ref;
   Derived d;
 };
@@ -94,12 +97,52 @@ struct TileArgs {
   int nb;              // FP64 shapelet kernel: order bucket
 };
 
+// ---------------------------------------------------------------------------
+// serving: a persistent kernel pulls (job slot, tile) items from a ring that
+// the host publishes in host-mapped memory.
+// ---------------------------------------------------------------------------
+constexpr int kServeSlots = 1024;
+constexpr uint64_t kRingSize = 1ull << 20;
+constexpr uint64_t kNoClaim = ~0ull;
+
+struct ServeJobDesc {
+  TileArgs a;            // tiling of the point/Gaussian pass (kPgChan-wide blocks)
+  DeriveArgs da;         // table items (when the job builds its tables)
+  FluxArgs fa;
+  int64_t ntiles;        // a.n_rb * a.n_cb
+  int64_t ntable;        // table items
+  uint64_t seq;          // sequence number of the tile phase (> 0, grows with publication)
+  uint64_t seq_table;    // sequence number of the table phase
+  uint64_t done_target;  // slot's tile counter value once this job's last tile is done
+  uint64_t table_target; // slot's table counter value once the last table item is done
+};
+
+struct ServeHost {       // host-mapped, coherent
+  uint64_t tail;         // tiles published (written by the host with release order)
+  uint64_t stop;         // non-zero: workers exit once idle
+  uint64_t started[kServeSlots];   // seq of the job whose first tile has started
+  uint64_t finished[kServeSlots];  // seq of the job whose last tile has finished
+  uint64_t tabled[kServeSlots];    // seq_table of the job whose tables are built
+  uint64_t ring[kRingSize];        // (slot << 48) | (table item << 47) | item index
+  ServeJobDesc jobs[kServeSlots];
+};
+
+struct ServeDev {        // device memory
+  uint64_t head;         // items claimed
+  uint64_t quit_epoch;   // launch epoch whose workers are to exit
+  uint64_t done[kServeSlots];
+  uint64_t tdone[kServeSlots];
+};
+
 // Host-side launchers (vp_kernels.hip).
 hipError_t launch_derive(const DeriveArgs &a, hipStream_t s);
 hipError_t launch_flux(const FluxArgs &a, hipStream_t s);
 hipError_t launch_tiles_build(const TileBuildArgs &a, int max_nmax, hipStream_t s);
 hipError_t launch_pg(const TileArgs &a, int prec, hipStream_t s);
 hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s);
+hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
+                        hipStream_t s);
+hipError_t serve_grid(int *grid);
 
 // sizes of per-shapelet tile storage
 inline int64_t a32_floats(int nmax) {

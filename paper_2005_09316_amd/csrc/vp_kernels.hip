@@ -102,10 +102,7 @@ __device__ __forceinline__ double hermite_phi0_mixed(double x) {
 
 // Direction cosines of every component relative to the phase centre, the
 // Gaussian envelope's quadratic form, and each shapelet's frame vectors.
-__global__ void k_derive(DeriveArgs a) {
-  const int J = a.P + a.G + a.S;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
+__device__ __forceinline__ void derive_one(const DeriveArgs &a, int j) {
   const double ra = a.ra[j], dec = a.dec[j];
   const double da = ra - a.ra0;
   const double sd = sin(dec), cd = cos(dec), sd0 = sin(a.dec0), cd0 = cos(a.dec0);
@@ -152,24 +149,36 @@ __global__ void k_derive(DeriveArgs a) {
   }
 }
 
-// S_j(nu_k) = S_ref (nu_k / nu_ref)^alpha * B_j(nu_k).
-__global__ void k_flux(FluxArgs a) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)a.J * a.Kpad) return;
+__global__ void k_derive(DeriveArgs a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < a.P + a.G + a.S) derive_one(a, j);
+}
+
+// S_j(nu_k) = S_ref (nu_k / nu_ref)^alpha * B_j(nu_k) for flat index
+// idx = j * Kpad + k (zero in the channel padding).
+__device__ __forceinline__ void flux_one(const FluxArgs &a, int64_t idx) {
   const int j = (int)(idx / a.Kpad), k = (int)(idx % a.Kpad);
   double S = 0.0;
   if (k < a.K) {
     const double nu = a.freq[k];
     S = a.sref[j] * pow(nu / a.nu_ref, a.alpha[j]);
     if (a.beam_fwhm > 0.0) {
-      const double4 p = a.d.pos[j];
-      const double rho = asin(sqrt(p.x * p.x + p.y * p.y));
+      // distance from the phase centre: sin(rho) = sqrt(l^2 + m^2)
+      const double dec = a.dec[j], da = a.ra[j] - a.ra0;
+      const double l = cos(dec) * sin(da);
+      const double m = sin(dec) * cos(a.dec0) - cos(dec) * sin(a.dec0) * cos(da);
+      const double rho = asin(sqrt(l * l + m * m));
       const double th = a.beam_fwhm * a.beam_nu_ref / nu;
       S *= exp(-4.0 * 0.69314718055994530942 * rho * rho / (th * th));
     }
   }
   a.d.flux32[idx] = (float)S;
   a.d.flux64[idx] = S;
+}
+
+__global__ void k_flux(FluxArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (int64_t)a.J * a.Kpad) flux_one(a, idx);
 }
 
 // Coefficient tiles.  Signed coefficients C''[n1][n2] = C[n1][n2] (-1)^floor((n1+n2)/2),
@@ -433,10 +442,32 @@ constexpr int kFoldSteps = 2;
 
 // ACC: accumulator of the tile's visibilities while shapelets are added
 // (double on the mixed path, float on the FP32-only path).
-template <typename ACC>
+// Contraction modes: FP32 MFMA, or the coefficients and the second axis's
+// Hermite values split into BF16 parts (x = hi + mid + lo) with the partial
+// products summed on v_mfma_f32_32x32x16_bf16: 3 parts / 6 products, or
+// 2 parts / 3 products.
+enum Contraction : int { kCmF32 = 0, kCmBf16x2 = 2, kCmBf16x3 = 3 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kAbfPerShp = 3 * kMBMax * 2 * kBf16Chunks * 64 * 8;  // BF16 elements, upper bound
+
+template <int CM>
+struct ShpA {
+  float A[kA32PerShp];
+};
+template <>
+struct ShpA<kCmBf16x2> {
+  uint4 A[kAbfPerShp / 8];
+};
+template <>
+struct ShpA<kCmBf16x3> {
+  uint4 A[kAbfPerShp / 8];
+};
+
+template <typename ACC, int CM = kCmF32>
 struct ShpSmem {
   ACC acc_re[kShpChan][kTileRows], acc_im[kShpChan][kTileRows];
-  float A[kA32PerShp];
+  ShpA<CM> a;
   double am[kTileRows], bm[kTileRows], t0[kTileRows];
 };
 
@@ -459,8 +490,8 @@ __device__ __forceinline__ float shp_phi0<float>(float x) {
 // Each wave owns 64 rows; a group of 32 visibilities (32 rows of one channel)
 // is the N dimension of the MFMA, lanes l and l + 32 holding the two K
 // halves.  REC is the recurrence type, DOT the envelope accumulator type.
-template <typename REC, typename DOT>
-__device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpSmem<DOT> &sm) {
+template <typename REC, typename DOT, int CM = kCmF32>
+__device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpSmem<DOT, CM> &sm) {
   constexpr int KB = kShpChan;
   const int k0 = cb * KB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -495,11 +526,22 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
   for (int j = 0; j < a.S; ++j) {
     const int N = a.t.nmax[j];
     const int MB = (N + 32) / 32, S4 = (N + 4) / 4;
+    const int NC = (N / 2 + 1 + 15) / 16;  // BF16 K steps (16 orders of one parity) per parity
     __syncthreads();
     {
-      const float *src = a.t.a32 + a.t.a32_off[j];
-      const int n32 = MB * 2 * S4 * 64;
-      for (int i = tid; i < n32; i += kTileRows) sm.A[i] = src[i];
+      if (CM == kCmF32) {
+        const float *src = a.t.a32 + a.t.a32_off[j];
+        const int n32 = MB * 2 * S4 * 64;
+        float *dst = (float *)&sm.a.A[0];
+        for (int i = tid; i < n32; i += kTileRows) dst[i] = src[i];
+      } else {
+        // hi, mid (and lo) parts, each MB * 2 * NC * 64 * 8 BF16 values
+        const int nbf = MB * 2 * NC * 64 * 8;
+        const int parts = CM == kCmBf16x3 ? 3 : 2;
+        const uint4 *src = (const uint4 *)(a.t.abf + a.t.abf_off[j]);
+        uint4 *dst = (uint4 *)&sm.a.A[0];
+        for (int i = tid; i < parts * nbf / 8; i += kTileRows) dst[i] = src[i];
+      }
       const double *fr = a.d.sframe + 12 * j;
       sm.am[tid] = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
       sm.bm[tid] = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
@@ -547,8 +589,84 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
             pa[4 * q + 2] = (DOT)(h ? r6 : r2);
             pa[4 * q + 3] = (DOT)(h ? r7 : r3);
           }
+          if (CM != kCmF32) {
+            // second axis in 32-order chunks: this lane's half of each chunk
+            // (orders 32 ch + 16 h + [0, 16)) split into BF16 parts, even
+            // orders feeding the real and odd orders the imaginary accumulator
+            const int nbf = MB * 2 * NC * 64 * 8;
+            const __bf16 *Ab = (const __bf16 *)&sm.a.A[0];
+            const int chmax = (N - 32 * mb) / 32 + 1;
+            REC pb_m1 = 0, pb_n = pb0;
+            for (int ch = 0; ch < chmax; ++ch) {
+              float lo16[16], hi16[16];
+              REC q_prev = pb_m1, q_cur = pb_n;
+#pragma unroll
+              for (int t = 0; t < 32; ++t) {
+                const REC q_next = herm_step<REC>(sxb, q_cur, q_prev, 32 * ch + t);
+                if (t < 16)
+                  lo16[t] = (float)q_cur;
+                else
+                  hi16[t - 16] = (float)q_cur;
+                q_prev = q_cur;
+                q_cur = q_next;
+              }
+              pb_m1 = q_prev;
+              pb_n = q_cur;
+              bf16x8 eh, em, el, oh, om, ol;
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const float ve = h ? hi16[2 * e] : lo16[2 * e];
+                const float vo = h ? hi16[2 * e + 1] : lo16[2 * e + 1];
+                eh[e] = (__bf16)ve;
+                oh[e] = (__bf16)vo;
+                const float re = ve - (float)eh[e], ro = vo - (float)oh[e];
+                em[e] = (__bf16)re;
+                om[e] = (__bf16)ro;
+                el[e] = (__bf16)(re - (float)em[e]);
+                ol[e] = (__bf16)(ro - (float)om[e]);
+              }
+              const int be_off = (((mb * 2 + 0) * NC + ch) * 64 + lane) * 8;
+              const int bo_off = (((mb * 2 + 1) * NC + ch) * 64 + lane) * 8;
+              const bf16x8 Aeh = *(const bf16x8 *)(Ab + be_off), Aoh = *(const bf16x8 *)(Ab + bo_off);
+              const bf16x8 Aem = *(const bf16x8 *)(Ab + nbf + be_off), Aom = *(const bf16x8 *)(Ab + nbf + bo_off);
+              floatx16 De, Do;
+              // smallest products first
+              if (CM == kCmBf16x3) {
+                const bf16x8 Ael = *(const bf16x8 *)(Ab + 2 * nbf + be_off);
+                const bf16x8 Aol = *(const bf16x8 *)(Ab + 2 * nbf + bo_off);
+                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aem, em, zero16, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aom, om, zero16, 0, 0, 0);
+                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ael, eh, De, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aol, oh, Do, 0, 0, 0);
+                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aeh, el, De, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aoh, ol, Do, 0, 0, 0);
+                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aem, eh, De, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aom, oh, Do, 0, 0, 0);
+              } else {
+                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aem, eh, zero16, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aom, oh, zero16, 0, 0, 0);
+              }
+              De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aeh, em, De, 0, 0, 0);
+              Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aoh, om, Do, 0, 0, 0);
+              De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aeh, eh, De, 0, 0, 0);
+              Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aoh, oh, Do, 0, 0, 0);
+#pragma unroll
+              for (int i = 0; i < 16; ++i) {
+                const DOT te = (DOT)De[i], to = (DOT)Do[i];
+                if ((i & 1) == 0) {
+                  xr = fma(pa[i], te, xr);
+                  xi = fma(pa[i], to, xi);
+                } else {
+                  xr = fma(pa[i], to, xr);
+                  xi = fma(pa[i], te, xi);
+                }
+              }
+            }
+            continue;
+          }
           // second axis: recurrence feeding the B operand, K restricted to the
           // triangle n1 + n2 <= N of this block
+          const float *A32 = (const float *)&sm.a.A[0];
           const int smax = (N - 32 * mb) / 4 + 1;
           REC pb_m1 = 0, pb_n = pb0;
           floatx16 De = zero16, Do = zero16;
@@ -569,8 +687,8 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
                 const float bo = (float)(h ? q3 : q1);
                 const int ie = ((mb * 2 + 0) * S4 + s4) * 64 + lane;
                 const int io = ((mb * 2 + 1) * S4 + s4) * 64 + lane;
-                De = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.A[ie], be, uu == 0 ? zero16 : De, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.A[io], bo, uu == 0 ? zero16 : Do, 0, 0, 0);
+                De = __builtin_amdgcn_mfma_f32_32x32x2f32(A32[ie], be, uu == 0 ? zero16 : De, 0, 0, 0);
+                Do = __builtin_amdgcn_mfma_f32_32x32x2f32(A32[io], bo, uu == 0 ? zero16 : Do, 0, 0, 0);
               }
             }
             // fold: xi += sum over this lane's rows of phi_n1(a) * T[n1]
@@ -624,11 +742,11 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
   }
 }
 
-template <typename REC, typename DOT>
+template <typename REC, typename DOT, int CM>
 __global__ __launch_bounds__(kTileRows) void k_shp_mfma(TileArgs a) {
-  __shared__ ShpSmem<DOT> sm;
+  __shared__ ShpSmem<DOT, CM> sm;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  shp_tile<REC, DOT>(a, tile % a.n_rb, tile / a.n_rb, sm);
+  shp_tile<REC, DOT, CM>(a, tile % a.n_rb, tile / a.n_rb, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,6 +857,146 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// serving: persistent kernel (continuous batching, mixed path)
+// ---------------------------------------------------------------------------
+
+// Every workgroup loops: claim the next published item (compare-and-swap on
+// a device counter), copy that job's arguments from host-mapped memory into
+// LDS, and either build a slice of the job's per-(sky, observation) tables
+// (table item) or run the point/Gaussian tile and then its two shapelet
+// half-tiles with the same device functions as the standalone kernels (so a
+// job's result is the same alone and in a mix).  Items are counted done per
+// job slot; the last one of a phase publishes the phase's sequence number to
+// the host.  Building tables here rather than in separate kernels matters:
+// this kernel occupies every CU, so other kernels would wait for it to drain.  A workgroup exits
+// when any workgroup of the launch has found nothing to claim for idle_ticks
+// (all exit together, after their current item), or when the host sets stop;
+// no workgroup ever waits on another.
+// Kept out of line so that its FP64 library calls do not add to the register
+// allocation of the tile path that shares the kernel.
+__device__ __noinline__ void serve_table_item(const ServeJobDesc &job, int64_t item, int tid) {
+  const int J = job.da.P + job.da.G + job.da.S;
+  const int64_t nder = (J + kTileRows - 1) / kTileRows;
+  if (item < nder) {
+    const int64_t j = item * kTileRows + tid;
+    if (j < J) derive_one(job.da, (int)j);
+  } else {
+    const int64_t idx = (item - nder) * kTileRows + tid;
+    if (idx < (int64_t)J * job.fa.Kpad) flux_one(job.fa, idx);
+  }
+}
+
+union ServeSmem {
+  PgSmem<float> pg;
+  ShpSmem<double> shp;
+};
+
+__global__ __launch_bounds__(kTileRows) void k_serve(ServeHost *H, ServeDev *D, uint64_t idle_ticks,
+                                                     uint64_t epoch) {
+  __shared__ ServeSmem sm;
+  __shared__ ServeJobDesc job;
+  __shared__ uint64_t s_claim, s_entry, s_seen;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_seen = 0;
+  for (;;) {
+    if (tid == 0) {
+      uint64_t claimed = kNoClaim;
+      const uint64_t t_idle = wall_clock64();
+      unsigned backoff = 1;
+      for (;;) {
+        if (__hip_atomic_load(&D->quit_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        // Relaxed, system-scope accesses: host-mapped memory is read uncached,
+        // and the ring entry and job arguments are read through addresses that
+        // depend on the claimed index, which orders them after the tail.  An
+        // acquire here would invalidate the XCD's L2 on every claim and throw
+        // away the component tables the other workgroups are streaming.
+        uint64_t h = __hip_atomic_load(&D->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t = __hip_atomic_load(&H->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (h < t) {
+          if (__hip_atomic_compare_exchange_strong(&D->head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)) {
+            claimed = h;
+            break;
+          }
+          continue;
+        }
+        if (__hip_atomic_load(&H->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (__hip_atomic_load(&D->quit_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (wall_clock64() - t_idle > idle_ticks) {
+          // the ring has been empty for idle_ticks: the whole launch exits
+          // (workers finish their current item first) so that the host can
+          // relaunch a full grid for the next job
+          __hip_atomic_store(&D->quit_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        for (unsigned i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
+        backoff = backoff < 64 ? 2 * backoff : 64;
+      }
+      s_claim = claimed;
+      if (claimed != kNoClaim)
+        s_entry = __hip_atomic_load(&H->ring[claimed & (kRingSize - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+    if (s_claim == kNoClaim) return;
+    const int slot = (int)(s_entry >> 48);
+    const bool table_item = (s_entry >> 47) & 1;
+    const int64_t tile = (int64_t)(s_entry & ((1ull << 47) - 1));
+    {
+      const uint64_t *src = (const uint64_t *)&H->jobs[slot];
+      uint64_t *dst = (uint64_t *)&job;
+      constexpr int words = (int)(sizeof(ServeJobDesc) / sizeof(uint64_t));
+      for (int i = tid; i < words; i += kTileRows)
+        dst[i] = __hip_atomic_load(&src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    const uint64_t item_seq = table_item ? job.seq_table : job.seq;
+    if (tid == 0 && item_seq > s_seen) {
+      // First item of a phase newer than any this workgroup has run: drop
+      // cached lines that may predate its inputs (buffers and tables can be
+      // reallocated and rewritten while this kernel runs).  A phase's inputs
+      // are complete before it is published and sequence numbers grow with
+      // publication, so one invalidation per newer sequence number suffices.
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_seen = item_seq;
+    }
+    __syncthreads();
+    if (table_item) {
+      // per-(sky, observation) tables: items [0, nder) derive kTileRows
+      // components each, the rest compute kTileRows flux-table entries each
+      serve_table_item(job, tile, tid);
+      __syncthreads();
+      if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        const uint64_t old = __hip_atomic_fetch_add(&D->tdone[slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == job.table_target)
+          __hip_atomic_store(&H->tabled[slot], job.seq_table, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      __syncthreads();
+      continue;
+    }
+    if (tid == 0 && tile == 0)
+      __hip_atomic_store(&H->started[slot], job.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const int rb = (int)(tile % job.a.n_rb), cb = (int)(tile / job.a.n_rb);
+    pg_tile<kMixed>(job.a, rb, cb, sm.pg);
+    __syncthreads();  // the tile's point/Gaussian sums are visible to the whole workgroup
+    if (job.a.S > 0) {
+      shp_tile<double, double>(job.a, rb, 2 * cb, sm.shp);
+      shp_tile<double, double>(job.a, rb, 2 * cb + 1, sm.shp);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // this tile's visibilities are written back to memory before the tile is
+      // counted; the job's last count therefore follows every tile's data, and
+      // the host flag follows the last count
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system-scope release: write back, no invalidate
+      const uint64_t old = __hip_atomic_fetch_add(&D->done[slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1 == job.done_target)
+        __hip_atomic_store(&H->finished[slot], job.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();  // LDS (job, tiles) is reused by the next claim
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -821,14 +1079,38 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) 
         hipLaunchKernelGGL(k_shp_fp64<96>, g, b, 0, s, a);
       break;
     case kFP32:
-      hipLaunchKernelGGL((k_shp_mfma<float, float>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_shp_mfma<float, float, kCmF32>), g, b, 0, s, a);
       break;
     case kMixed:
-      hipLaunchKernelGGL((k_shp_mfma<double, double>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmF32>), g, b, 0, s, a);
+      break;
+    case kMixedBf16:
+      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmBf16x3>), g, b, 0, s, a);
+      break;
+    case kMixedBf16x2:
+      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmBf16x2>), g, b, 0, s, a);
       break;
     default:
       return hipErrorNotSupported;
   }
+  return hipGetLastError();
+}
+
+hipError_t serve_grid(int *grid) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve, kTileRows, 0);
+  if (e != hipSuccess) return e;
+  *grid = cus * (per > 0 ? per : 1);
+  return hipSuccess;
+}
+
+hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
+                        hipStream_t s) {
+  hipError_t e = upload_tables();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_serve, dim3(grid), dim3(kTileRows), 0, s, host_dev, dev, idle_ticks, epoch);
   return hipGetLastError();
 }
 

@@ -26,10 +26,11 @@ struct DeviceMem {
 };
 
 struct DerivedEntry {
-  Derived d;
+  Derived d{};
   DeviceMem mem;
-  hipEvent_t ready = nullptr;  // recorded after the tables are built
+  hipEvent_t ready = nullptr;  // recorded after kernels built the tables (null when the serving kernel did)
   hipStream_t ready_stream = nullptr;
+  bool building = false;       // true while the serving kernel builds the tables (guarded by ctx->mu)
 };
 
 struct ProfRecord {
@@ -64,10 +65,23 @@ int run_tiles(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs *ob
               void *vis, int subtract, hipStream_t stream);
 int check_call(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs *obs, int precision, int dtype,
                void *vis);
+// Per-(sky, observation) tables, built on `stream` at first use and cached;
+// later callers on other streams wait for the build.
+int get_derived(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs *obs, hipStream_t stream,
+                DerivedEntry **out);
+// Serving: find the pair's tables, or allocate them unbuilt (*build = true:
+// the caller builds them and calls derived_built).
+int serve_derived(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs *obs, DerivedEntry **out,
+                  bool *build);
+bool derived_ready(vp_ctx *ctx, DerivedEntry *d);
+void derived_built(vp_ctx *ctx, DerivedEntry *d);
+DeriveArgs make_derive_args(const struct ::vp_sky *sky, const struct ::vp_obs *obs, const Derived &d);
+FluxArgs make_flux_args(const struct ::vp_sky *sky, const struct ::vp_obs *obs, const Derived &d);
 void drop_derived(vp_ctx *ctx, uint64_t sky_id, uint64_t obs_id);
 void drop_all_derived(vp_ctx *ctx);
 
 // serving hooks (vp_serve.cpp)
+uint64_t job_footprint(const struct ::vp_sky *sky, const struct ::vp_obs *obs, int dtype);
 bool serve_pending(vp_ctx *ctx);
 void serve_shutdown(vp_ctx *ctx);
 

@@ -49,6 +49,9 @@ def _predict_rows(ctx, obs, sky, prec, dtype, rows):
 @pytest.mark.parametrize("cfg,nrows_sample", [(1, 192), (2, 384)])
 @pytest.mark.parametrize("prec,dtype,tol", [(vp.VP_PREC_MIXED, vp.VP_C64, 1e-6),
                                             (vp.VP_PREC_MIXED, vp.VP_C128, 1e-6),
+                                            (vp.VP_PREC_MIXED_BF16, vp.VP_C128, 1e-6),
+                                            (vp.VP_PREC_MIXED_BF16X2, vp.VP_C128, None),
+                                            (vp.VP_PREC_FP32, vp.VP_C64, None),
                                             (vp.VP_PREC_FP64, vp.VP_C128, 1e-11)])
 def test_fullsize_sampled(ctx, cfg, nrows_sample, prec, dtype, tol):
     obs, sky = synth.make_config(cfg)
@@ -57,8 +60,10 @@ def test_fullsize_sampled(ctx, cfg, nrows_sample, prec, dtype, tol):
     got, dt = _predict_rows(ctx, obs, sky, prec, dtype, rows)
     ref = oracle.predict(obs, sky, rows=rows)
     err = oracle.error_metric(got, ref, obs, sky)
-    _log("  gpu %.1f ms (first call, with table build); sampled error / total flux = %.3e" % (dt * 1e3, err))
-    assert err <= tol
+    _log("  gpu %.1f ms (first call, with table build); sampled error / total flux = %.3e%s"
+         % (dt * 1e3, err, "" if tol else " (reported, not gated)"))
+    if tol:
+        assert err <= tol
 
 
 def test_large_peel_sampled(ctx):

@@ -21,7 +21,7 @@ from tests.helpers import Handles, run
 
 pytestmark = pytest.mark.gpu
 
-TOL = {vp.VP_PREC_FP64: 1e-11, vp.VP_PREC_MIXED: 1e-6}
+TOL = {vp.VP_PREC_FP64: 1e-11, vp.VP_PREC_MIXED: 1e-6, vp.VP_PREC_MIXED_BF16: 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +65,7 @@ def _log(*a):
 
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("prec,dtype", [(vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C128),
-                                        (vp.VP_PREC_MIXED, vp.VP_C64)])
+                                        (vp.VP_PREC_MIXED, vp.VP_C64), (vp.VP_PREC_MIXED_BF16, vp.VP_C128)])
 def test_predict_matches_oracle(ctx, name, prec, dtype):
     obs, sky, ref = _ref(name)
     _log("case", name, "prec", prec, "dtype", dtype, "vis", obs.n_vis)
@@ -80,13 +80,15 @@ def test_predict_matches_oracle(ctx, name, prec, dtype):
     assert err <= tol
 
 
-@pytest.mark.parametrize("name", ["tiny", "fornax-mid"])
-def test_fp32_only_path_is_reported(ctx, name):
+@pytest.mark.parametrize("name", ["tiny", "fornax-mid", "nmax-limit"])
+@pytest.mark.parametrize("prec", [vp.VP_PREC_FP32, vp.VP_PREC_MIXED_BF16X2])
+def test_reported_paths(ctx, name, prec):
+    """FP32-only and 2-way BF16 paths: error reported, not gated."""
     obs, sky, ref = _ref(name)
     with Handles(ctx, obs, sky) as h:
-        got = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_FP32, vp.VP_C64)
+        got = run(ctx, h.obs, h.sky, obs, prec, vp.VP_C64)
     err = oracle.error_metric(got, ref, obs, sky)
-    _log("FP32-only path, case %s: error / total flux = %.3e (not gated)" % (name, err))
+    _log("precision %d, case %s: error / total flux = %.3e (not gated)" % (prec, name, err))
     assert np.all(np.isfinite(got))
 
 
