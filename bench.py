@@ -38,6 +38,19 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 #   per (row, component): u l + v m + w (n - 1), 3 FMAs shared by the row's channels
 SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 9, 13, 3
 
+# HBM bytes per launch of the point/Gaussian kernel on this workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (summary in
+# profiles/k_pg_tile_mwa-like_hbm-traffic.md), valid for the kernel source
+# whose hash is recorded; reported as null once that source changes.
+PG_TRAFFIC = {"bytes": 148.1e6 + 29.1e6, "source_sha256_16": "9a001eb5db053faa"}
+
+
+def _pg_source_hash():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2005_09316_amd", "csrc", "vp_kernels.hip")).read()
+    a, b = src.index("// point + Gaussian tile kernel"), src.index("// shapelet tile on MFMA")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -121,6 +134,44 @@ def serve_stream(n_requests, rate_hz, budget_bytes):
     return out
 
 
+def paper_cost_comparison():
+    """The paper's Sec. 5.3 comparison on this chip: time to predict the peel
+    observation from the MS CLEAN-like model (4540 points + 1791 Gaussians)
+    and from the two p_max = 86 shapelet lobes (7656 basis functions), on the
+    mixed and FP64 paths.  The paper found the shapelet model more than twice
+    as expensive on its GPU simulator."""
+    import torch
+
+    import synth
+    from paper_2005_09316_amd import vp
+
+    obs, clean, lobes = synth.make_paper_cost_comparison()
+    ctx = vp.vp_create_ctx(0, 0)
+    oh = vp.vp_create_obs(ctx, obs)
+    out = torch.empty((obs.n_time, obs.n_bl, obs.n_chan), dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {"n_vis": obs.n_vis, "clean_components": clean.n_point + clean.n_gauss,
+           "shapelet_basis_functions": lobes.n_basis()}
+    for name, sky in (("clean", clean), ("shapelet", lobes)):
+        sh = vp.vp_create_sky(ctx, sky)
+        for pname, prec in (("mixed", vp.VP_PREC_MIXED), ("fp64", vp.VP_PREC_FP64)):
+            vp.vp_predict(ctx, sh, oh, prec, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                vp.vp_predict(ctx, sh, oh, prec, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize()
+            res["%s_%s_ms" % (name, pname)] = (time.perf_counter() - t0) * 1e3 / reps
+        vp.vp_destroy_sky(sh)
+    for pname in ("mixed", "fp64"):
+        res["shapelet_over_clean_%s" % pname] = res["shapelet_%s_ms" % pname] / res["clean_%s_ms" % pname]
+    vp.vp_destroy_obs(oh)
+    vp.vp_destroy_ctx(ctx)
+    _log("paper cost comparison: %s" % json.dumps(res))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +184,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-paper-cost", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (its HBM counters scale the kernels')")
     args = ap.parse_args()
@@ -213,7 +265,9 @@ def main():
     achieved = slots / (pg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_pg_tile<mixed>", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s (VALU issue slots)",
-                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": PG_TRAFFIC["bytes"] if _pg_source_hash() == PG_TRAFFIC["source_sha256_16"] else None,
+                "traffic_unit": "bytes per launch (HBM read + write)",
                 "kernel_ms": round(pg_ms, 4), "shapelet_kernel_ms": round(shp_ms, 4)}
 
     # ---- sampled parity + CPU baseline (oracle) ----
@@ -241,6 +295,8 @@ def main():
     del out, out64
     torch.cuda.empty_cache()
 
+    paper_cost = None if args.no_paper_cost else paper_cost_comparison()
+
     serving = None
     if not args.no_serve:
         serving = serve_stream(args.serve_requests, args.serve_rate, int(args.serve_budget_gb * 1e9))
@@ -261,6 +317,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "paper_cost_comparison": paper_cost,
     }
     print(json.dumps(line), flush=True)
 

@@ -129,6 +129,7 @@ struct ServeHost {       // host-mapped, coherent
 
 struct ServeDev {        // device memory
   uint64_t head;         // items claimed
+  uint64_t tail_cache;   // largest published-item count any worker has read from the host
   uint64_t quit_epoch;   // launch epoch whose workers are to exit
   uint64_t done[kServeSlots];
   uint64_t tdone[kServeSlots];

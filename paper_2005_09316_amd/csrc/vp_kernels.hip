@@ -895,9 +895,13 @@ __global__ __launch_bounds__(kTileRows) void k_serve(ServeHost *H, ServeDev *D, 
                                                      uint64_t epoch) {
   __shared__ ServeSmem sm;
   __shared__ ServeJobDesc job;
-  __shared__ uint64_t s_claim, s_entry, s_seen;
+  __shared__ uint64_t s_claim, s_entry, s_seen, s_cached_seq;
+  __shared__ int s_cached_slot, s_cached_table, s_reload;
   const int tid = threadIdx.x;
-  if (tid == 0) s_seen = 0;
+  if (tid == 0) {
+    s_seen = 0;
+    s_cached_slot = -1;
+  }
   for (;;) {
     if (tid == 0) {
       uint64_t claimed = kNoClaim;
@@ -910,8 +914,14 @@ __global__ __launch_bounds__(kTileRows) void k_serve(ServeHost *H, ServeDev *D, 
         // depend on the claimed index, which orders them after the tail.  An
         // acquire here would invalidate the XCD's L2 on every claim and throw
         // away the component tables the other workgroups are streaming.
+        // The host's tail is read over PCIe only when the device-side copy says
+        // the ring is empty; claims themselves touch device memory only.
         uint64_t h = __hip_atomic_load(&D->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t t = __hip_atomic_load(&H->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        uint64_t t = __hip_atomic_load(&D->tail_cache, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h >= t) {
+          t = __hip_atomic_load(&H->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (t > h) __hip_atomic_fetch_max(&D->tail_cache, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (h < t) {
           if (__hip_atomic_compare_exchange_strong(&D->head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT)) {
@@ -933,15 +943,28 @@ __global__ __launch_bounds__(kTileRows) void k_serve(ServeHost *H, ServeDev *D, 
         backoff = backoff < 64 ? 2 * backoff : 64;
       }
       s_claim = claimed;
-      if (claimed != kNoClaim)
-        s_entry = __hip_atomic_load(&H->ring[claimed & (kRingSize - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (claimed != kNoClaim) {
+        const uint64_t e =
+            __hip_atomic_load(&H->ring[claimed & (kRingSize - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        s_entry = e;
+        // The job arguments in LDS are reused when the item belongs to the same
+        // slot and phase and the slot still carries the same sequence number
+        // (the host rewrites a slot only between jobs or phases, changing it).
+        const int slot = (int)(e >> 48), table = (int)((e >> 47) & 1);
+        const uint64_t *seqp = table ? &H->jobs[slot].seq_table : &H->jobs[slot].seq;
+        const uint64_t seq = __hip_atomic_load(seqp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        s_reload = !(slot == s_cached_slot && table == s_cached_table && seq == s_cached_seq);
+        s_cached_slot = slot;
+        s_cached_table = table;
+        s_cached_seq = seq;
+      }
     }
     __syncthreads();
     if (s_claim == kNoClaim) return;
     const int slot = (int)(s_entry >> 48);
     const bool table_item = (s_entry >> 47) & 1;
     const int64_t tile = (int64_t)(s_entry & ((1ull << 47) - 1));
-    {
+    if (s_reload) {
       const uint64_t *src = (const uint64_t *)&H->jobs[slot];
       uint64_t *dst = (uint64_t *)&job;
       constexpr int words = (int)(sizeof(ServeJobDesc) / sizeof(uint64_t));

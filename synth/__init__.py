@@ -427,6 +427,30 @@ def make_config(index: int, seed: Optional[int] = None, **over):
     raise ValueError("workload %d has no single (obs, sky); use make_requests for the serving stream" % index)
 
 
+def make_paper_cost_comparison(seed: Optional[int] = None):
+    """The paper's model-cost comparison (Sec. 5.3): one peel observation
+    (MWA phase I layout, 15 x 8 s = 2 min, 384 x 80 kHz), phase-centred on
+    the source, predicted either from an MS CLEAN-like model of 4540 points
+    and 1791 Gaussians or from two shapelet lobes with p_max = 86 (7656 basis
+    functions).  Both models carry 500 Jy at 180 MHz, spectral index -0.8, and
+    lie within 0.5 deg of the centre.  Returns (obs, clean_sky, shapelet_sky)."""
+    rng = np.random.default_rng(SEED_BASE + 10 if seed is None else seed)
+    obs = make_obs(rng, 128, 15, channels(182e6, 80e3, 384))
+    half = math.radians(0.5)
+    clean = make_sky(rng, n_point=4540, n_gauss=1791, shapelet_nmax=[], cap_rad=half,
+                     point_flux=lambda r, n: r.exponential(1.0, n), alpha_mean=-0.8, alpha_sd=0.0)
+    tot = clean.p_sref.sum() + clean.g_sref.sum()
+    clean.p_sref = clean.p_sref * 500.0 / tot
+    clean.g_sref = clean.g_sref * 500.0 / tot
+    off = math.radians(0.3)
+    ra, dec = offset_to_radec(np.array([off, off]), np.array([math.pi / 2, -math.pi / 2]))
+    lobes = make_sky(rng, n_point=0, n_gauss=0, shapelet_nmax=[86, 86], cap_rad=half,
+                     point_flux=_lu(1, 2), shapelet_sref=[250.0, 250.0], tau=20.0,
+                     beta=([15 * ARCMIN, 25 * ARCMIN], [15 * ARCMIN, 25 * ARCMIN]),
+                     alpha_mean=-0.8, alpha_sd=0.0, shapelet_positions=(ra, dec))
+    return obs, clean, lobes
+
+
 @dataclasses.dataclass
 class Request:
     kind: str  # "predict" or "subtract"
