@@ -13,7 +13,13 @@ The JSON line carries:
                   its mean duration (HIP events on the launch stream) against
                   the chip's VALU issue peak;
   cpu_baseline -- the FP64 oracle on a bounded sample of rows, on the host's
-                  cores, which also checks the GPU output on those rows.
+                  cores, which also checks the GPU output on those rows;
+  shapelet_contraction -- the shapelet kernel alone on the Fornax-like
+                  workload (two lobes, n1 + n2 <= 70), per contraction mode:
+                  algorithmic contraction FLOP/s (2 p_tot per visibility and
+                  shapelet) against the FP32 MFMA peak, and the MFMA work the
+                  kernel issues against the peak of the instruction type used.
+                  `--only-shapelets` runs this leg alone (for profiling).
 """
 from __future__ import annotations
 
@@ -43,6 +49,81 @@ SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 9, 13, 3
 # profiles/k_pg_tile_mwa-like_hbm-traffic.md), valid for the kernel source
 # whose hash is recorded; reported as null once that source changes.
 PG_TRAFFIC = {"bytes": 148.1e6 + 29.1e6, "source_sha256_16": "9a001eb5db053faa"}
+
+
+# dense MFMA peaks (TFLOP/s)
+MFMA_PEAK_F32 = 157.3
+MFMA_PEAK_BF16 = 2500.0
+
+
+def _shp_mfma_flops(nmax, n_vis, mode):
+    """MFMA flops the shapelet kernel issues per launch: per 32 visibilities and
+    32 x 32 coefficient block, K steps of 4 orders on v_mfma_f32_32x32x2f32
+    (2 per step, 4096 flops each; only steps inside the triangle), or 2 parities
+    x 6 (BF16 x3) or 3 (BF16 x2) v_mfma_f32_32x32x16_bf16 (32768 flops each)."""
+    total = 0.0
+    for N in nmax:
+        q = N // 32
+        for ch in range(q + 1):
+            for mb in range(q - ch + 1):
+                if mode == "f32":
+                    total += 2 * min(8, (N - 32 * (ch + mb)) // 4 + 1) * 4096
+                else:
+                    total += 2 * (6 if mode == "bf16x3" else 3) * 32768
+    return total * n_vis / 32.0
+
+
+def shapelet_contraction(reps=5, check_rows=48):
+    """Shapelet kernel on the Fornax-like workload, per contraction mode."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2005_09316_amd import vp
+
+    obs, sky = synth.make_config(2)
+    ctx = vp.vp_create_ctx(0, 0)
+    oh, sh = vp.vp_create_obs(ctx, obs), vp.vp_create_sky(ctx, sky)
+    nrows, K = obs.n_time * obs.n_bl, obs.n_chan
+    out = torch.empty((nrows, K), dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    ptot = sum((int(n) + 1) * (int(n) + 2) // 2 for n in sky.s_nmax)
+    alg_flops = 2.0 * ptot * obs.n_vis
+    rows = np.sort(np.random.default_rng(6).choice(nrows, check_rows, replace=False))
+    ref = oracle.predict(obs, sky, rows=rows)
+    res = {"workload": synth.CONFIG_NAMES[2], "n_vis": obs.n_vis, "nmax": [int(n) for n in sky.s_nmax],
+           "algorithmic_flops_per_launch": alg_flops, "modes": {}}
+    for name, prec, mode, peak in (("mixed_fp32_mfma", vp.VP_PREC_MIXED, "f32", MFMA_PEAK_F32),
+                                   ("mixed_bf16x3", vp.VP_PREC_MIXED_BF16, "bf16x3", MFMA_PEAK_BF16)):
+        vp.vp_predict(ctx, sh, oh, prec, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
+        torch.cuda.synchronize()
+        vp.vp_profile(ctx, True)
+        vp.vp_profile_read(ctx)
+        for _ in range(reps):
+            vp.vp_predict(ctx, sh, oh, prec, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
+        torch.cuda.synchronize()
+        c, t = vp.vp_profile_read(ctx)
+        vp.vp_profile(ctx, False)
+        ms = float(t[2] / max(c[2], 1))
+        got = out[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        err = oracle.error_metric(got, ref, obs, sky)
+        issued = _shp_mfma_flops(sky.s_nmax, obs.n_vis, mode)
+        r = {"kernel_ms": round(ms, 4),
+             "algorithmic_tflops": round(alg_flops / ms / 1e9, 2),
+             "frac_of_fp32_mfma_peak": round(alg_flops / ms / 1e9 / MFMA_PEAK_F32, 4),
+             "issued_mfma_tflops": round(issued / ms / 1e9, 2),
+             "issued_frac_of_own_peak": round(issued / ms / 1e9 / peak, 4),
+             "own_peak_tflops": peak,
+             "sampled_err_vs_oracle": err}
+        res["modes"][name] = r
+        _log("shapelet kernel %s: %.3f ms, %.1f TFLOP/s algorithmic (%.1f%% of FP32 MFMA peak), "
+             "err %.2e" % (name, ms, r["algorithmic_tflops"], 100 * r["frac_of_fp32_mfma_peak"], err))
+    vp.vp_destroy_sky(sh)
+    vp.vp_destroy_obs(oh)
+    vp.vp_destroy_ctx(ctx)
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
 def _pg_source_hash():
@@ -185,6 +266,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper-cost", action="store_true")
+    ap.add_argument("--no-shapelets", action="store_true", help="skip the shapelet-contraction leg")
+    ap.add_argument("--only-shapelets", action="store_true",
+                    help="run only the shapelet-contraction leg and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (its HBM counters scale the kernels')")
     args = ap.parse_args()
@@ -197,6 +281,10 @@ def main():
 
     import synth
     from paper_2005_09316_amd import vp
+
+    if args.only_shapelets:
+        print(json.dumps(shapelet_contraction()), flush=True)
+        return
 
     t_gen = time.time()
     obs, sky = synth.make_config(1)
@@ -296,6 +384,7 @@ def main():
     torch.cuda.empty_cache()
 
     paper_cost = None if args.no_paper_cost else paper_cost_comparison()
+    shp = None if args.no_shapelets else shapelet_contraction()
 
     serving = None
     if not args.no_serve:
@@ -318,6 +407,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "paper_cost_comparison": paper_cost,
+        "shapelet_contraction": shp,
     }
     print(json.dumps(line), flush=True)
 

@@ -17,10 +17,20 @@ constexpr int kShpChan = 4;    // channels per shapelet tile
 constexpr int kChunk = 64;     // components staged in LDS at a time
 constexpr int kFlush = 8;      // components summed plainly before a Kahan step
 constexpr int kNmaxLimit = 96; // largest n1 + n2
-constexpr int kMBMax = 4;      // 32-row M blocks of the n1 axis: ceil(97 / 32)
-constexpr int kS4Max = 25;     // K steps of 4 orders: ceil(97 / 4)
-constexpr int kA32PerShp = kMBMax * 2 * kS4Max * 64;  // floats, upper bound
-constexpr int kBf16Chunks = 4;  // 16-wide K steps of one parity: ceil(49 / 16)
+constexpr int kMBMax = 4;      // 32-row blocks of the n1 axis: ceil(97 / 32)
+
+// The MFMA shapelet kernels keep only the 32 x 32 blocks of the signed
+// coefficient matrix (32 rows of n1 by 32 orders of n2) that meet the
+// triangle n1 + n2 <= N: block (chunk ch, row block mb) with
+// 32 (ch + mb) <= N, chunk-major.  With q = N / 32 there are
+// (q + 1)(q + 2) / 2 of them.
+__host__ __device__ inline int shp_pairs(int nmax) {
+  const int q = nmax / 32;
+  return (q + 1) * (q + 2) / 2;
+}
+constexpr int kPairsMax = (kNmaxLimit / 32 + 1) * (kNmaxLimit / 32 + 2) / 2;
+constexpr int kA32PerPair = 2 * 8 * 64;  // floats: [parity][K step of 2 orders][lane]
+constexpr int kAbfPerPair = 2 * 64 * 8;  // BF16 values of one split part: [parity][lane][8]
 
 enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4 };
 
@@ -41,7 +51,7 @@ struct ShpTiles {
   const double *c64;       // dense signed coefficients [n1][ld], FP64
   const int64_t *c64_off;  // [S]
   const int32_t *c64_ld;   // [S] leading dimension (multiple of 8)
-  const uint16_t *abf;     // BF16 split A tiles: [part][mb][par][chunk][64][8]
+  const uint16_t *abf;     // BF16 split A tiles: [part][pair][parity][64][8]
   const int64_t *abf_off;  // [S]
   const int32_t *nmax;     // [S]
 };
@@ -146,19 +156,9 @@ hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks,
 hipError_t serve_grid(int *grid);
 
 // sizes of per-shapelet tile storage
-inline int64_t a32_floats(int nmax) {
-  int mb = (nmax + 32) / 32, s4 = (nmax + 4) / 4;
-  return (int64_t)mb * 2 * s4 * 64;
-}
+inline int64_t a32_floats(int nmax) { return (int64_t)shp_pairs(nmax) * kA32PerPair; }
 inline int c64_ld(int nmax) { return ((nmax + 1) + 7) / 8 * 8; }
 inline int64_t c64_doubles(int nmax) { return (int64_t)(nmax + 1) * c64_ld(nmax); }
-inline int bf16_chunks(int nmax) {
-  // even orders 0, 2, ... <= nmax: nmax/2 + 1 values; 16 per K step
-  return (nmax / 2 + 1 + 15) / 16;
-}
-inline int64_t abf_elems(int nmax) {
-  int mb = (nmax + 32) / 32;
-  return (int64_t)3 * mb * 2 * bf16_chunks(nmax) * 64 * 8;
-}
+inline int64_t abf_elems(int nmax) { return (int64_t)3 * shp_pairs(nmax) * kAbfPerPair; }
 
 }  // namespace vp

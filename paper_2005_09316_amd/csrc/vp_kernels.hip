@@ -41,6 +41,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __constant__ double c_sqn[128];   // sqrt(n)
 __constant__ double c_isqn1[128]; // 1 / sqrt(n + 1)
+__constant__ double c_ab64[128][2]; // (sqrt(2 / (n + 1)), sqrt(n / (n + 1)))
+__constant__ float c_ab32[128][2];  // the same, rounded to FP32
 
 static constexpr double kPiM14 = 0.75112554446494248285870300477622; // pi^(-1/4)
 static constexpr double kHalfLog2e = 0.72134752044448170367996234050095; // log2(e) / 2
@@ -82,18 +84,6 @@ __device__ __forceinline__ void kahan_add(T &sum, T &cmp, T x) {
   const T t = sum + y;
   cmp = (t - sum) - y;
   sum = t;
-}
-
-// phi_0 = pi^(-1/4) exp(-x^2/2) with the exponent split into integer and
-// fractional powers of two: the fraction goes through the FP32 exp2 unit, the
-// integer part is applied exactly, so the value keeps full FP32 relative
-// accuracy down to FP64 underflow.
-__device__ __forceinline__ double hermite_phi0_mixed(double x) {
-  const double e = x * x * kHalfLog2e;
-  const double ei = floor(e);
-  const float ef = (float)(e - ei);
-  const double p = (double)__builtin_amdgcn_exp2f(-ef) * kPiM14;
-  return ei > 1100.0 ? 0.0 : ldexp(p, -(int)ei);
 }
 
 // ---------------------------------------------------------------------------
@@ -183,12 +173,16 @@ __global__ void k_flux(FluxArgs a) {
 
 // Coefficient tiles.  Signed coefficients C''[n1][n2] = C[n1][n2] (-1)^floor((n1+n2)/2),
 // so that xi = sum_{n1+n2 even} C'' phi phi + i sum_{n1+n2 odd} C'' phi phi
-// equals sum C i^(n1+n2) phi phi.  Layouts:
-//   a32: [mb][parity][s4][lane]: lane l supplies A[row = l % 32][k = l / 32] of
-//        the MFMA for n1 = 32 mb + l % 32, n2 = 4 s4 + 2 (l / 32) + parity;
-//   c64: [n1][ld], zero outside the triangle;
-//   abf: [part][mb][parity][chunk][lane][8] BF16 hi/mid/lo splits of a32's
-//        values for K = 16 steps: n2 = 32 chunk + 2 (8 (l / 32) + e) + parity.
+// equals sum C i^(n1+n2) phi phi.  The MFMA tiles hold the 32 x 32 blocks that
+// meet the triangle, in pair order (chunk ch of 32 n2-orders outer, row block
+// mb inner, 32 (ch + mb) <= N):
+//   a32: [pair][parity][s][lane]: lane l supplies A[row = l % 32][k = l / 32] of
+//        the 32x32x2 FP32 MFMA for n1 = 32 mb + l % 32,
+//        n2 = 32 ch + 4 s + 2 (l / 32) + parity;
+//   abf: [part][pair][parity][lane][8]: BF16 hi/mid/lo splits for the
+//        32x32x16 MFMA, element e of lane l: n1 = 32 mb + l % 32,
+//        n2 = 32 ch + 16 (l / 32) + 2 e + parity;
+//   c64: [n1][ld], zero outside the triangle.
 __device__ __forceinline__ double signed_coeff(const double *c, int N, int n1, int n2) {
   if (n1 < 0 || n2 < 0 || n1 > N || n2 > N - n1) return 0.0;
   const int64_t off = (int64_t)n1 * (N + 1) - (int64_t)n1 * (n1 - 1) / 2;
@@ -204,18 +198,29 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// (chunk, row block) of pair p; q = N / 32
+__device__ __forceinline__ void pair_coords(int q, int p, int &ch, int &mb) {
+  ch = 0;
+  while (p > q - ch) {
+    p -= q - ch + 1;
+    ++ch;
+  }
+  mb = p;
+}
+
 __global__ void k_tiles(TileBuildArgs a) {
   const int s = blockIdx.y;
   if (s >= a.S) return;
   const int N = a.nmax[s];
   const double *C = a.coeffs + a.coeff_off[s];
-  const int MB = (N + 32) / 32, S4 = (N + 4) / 4;
+  const int q = N / 32, npairs = shp_pairs(N);
   // FP32 MFMA tiles
-  const int n32 = MB * 2 * S4 * 64;
+  const int n32 = npairs * kA32PerPair;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += gridDim.x * blockDim.x) {
-    const int lane = i & 63, rest = i >> 6;
-    const int s4 = rest % S4, mp = rest / S4, par = mp & 1, mb = mp >> 1;
-    const int n1 = 32 * mb + (lane & 31), n2 = 4 * s4 + 2 * (lane >> 5) + par;
+    const int lane = i & 63, st = (i >> 6) & 7, par = (i >> 9) & 1, p = i >> 10;
+    int ch, mb;
+    pair_coords(q, p, ch, mb);
+    const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 4 * st + 2 * (lane >> 5) + par;
     a.a32[a.a32_off[s] + i] = (float)signed_coeff(C, N, n1, n2);
   }
   // FP64 dense
@@ -225,12 +230,12 @@ __global__ void k_tiles(TileBuildArgs a) {
     a.c64[a.c64_off[s] + i] = signed_coeff(C, N, n1, n2);
   }
   // BF16 three-way split tiles
-  const int NC = (N / 2 + 1 + 15) / 16;
-  const int nbf = MB * 2 * NC * 64 * 8;
+  const int nbf = npairs * kAbfPerPair;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbf; i += gridDim.x * blockDim.x) {
-    const int e = i & 7, lane = (i >> 3) & 63, rest = i >> 9;
-    const int ch = rest % NC, mp = rest / NC, par = mp & 1, mb = mp >> 1;
-    const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 2 * (8 * (lane >> 5) + e) + par;
+    const int e = i & 7, lane = (i >> 3) & 63, par = (i >> 9) & 1, p = i >> 10;
+    int ch, mb;
+    pair_coords(q, p, ch, mb);
+    const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 16 * (lane >> 5) + 2 * e + par;
     const float x = (float)signed_coeff(C, N, n1, n2);
     const uint16_t hi = bf16_rne(x);
     const float r1 = x - bf16_to_f(hi);
@@ -421,27 +426,21 @@ __device__ __forceinline__ R herm_step(R sx, R pn, R pm1, int n) {
   return (R)c_isqn1[n] * fma(sx, pn, -(R)c_sqn[n] * pm1);
 }
 
+// The same recurrence as phi_{n+1} = alpha_n x phi_n - beta_n phi_{n-1} with
+// alpha_n = sqrt(2 / (n + 1)) and beta_n = sqrt(n / (n + 1)): both products
+// with the constants are independent of phi_n, so one FMA per order sits on
+// the dependency chain.
 template <typename R>
-__device__ __forceinline__ R herm_phi0(R x);
+__device__ __forceinline__ R herm_next(R x, R pn, R pm1, int n);
 template <>
-__device__ __forceinline__ double herm_phi0<double>(double x) {
-  return hermite_phi0_mixed(x);
+__device__ __forceinline__ double herm_next<double>(double x, double pn, double pm1, int n) {
+  return fma(c_ab64[n][0] * x, pn, -c_ab64[n][1] * pm1);
 }
 template <>
-__device__ __forceinline__ float herm_phi0<float>(float x) {
-  return (float)kPiM14 * __builtin_amdgcn_exp2f(-x * x * (float)kHalfLog2e);
+__device__ __forceinline__ float herm_next<float>(float x, float pn, float pm1, int n) {
+  return fmaf(c_ab32[n][0] * x, pn, -c_ab32[n][1] * pm1);
 }
 
-// MFMA K steps summed in the FP32 accumulator before the partial n1 sum is
-// folded into the FP64 envelope accumulator.  The signed coefficients cancel
-// heavily (sum |C| is hundreds of times |xi(0)| for the synthetic skies), so
-// an FP32 sum over all orders loses ~1e-6 of the envelope; folding every
-// 2 steps (8 orders) keeps the loss near 4e-7 of total flux on the
-// shapelet-dominated workload.
-constexpr int kFoldSteps = 2;
-
-// ACC: accumulator of the tile's visibilities while shapelets are added
-// (double on the mixed path, float on the FP32-only path).
 // Contraction modes: FP32 MFMA, or the coefficients and the second axis's
 // Hermite values split into BF16 parts (x = hi + mid + lo) with the partial
 // products summed on v_mfma_f32_32x32x16_bf16: 3 parts / 6 products, or
@@ -449,26 +448,27 @@ constexpr int kFoldSteps = 2;
 enum Contraction : int { kCmF32 = 0, kCmBf16x2 = 2, kCmBf16x3 = 3 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kAbfPerShp = 3 * kMBMax * 2 * kBf16Chunks * 64 * 8;  // BF16 elements, upper bound
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 
+// LDS of the shapelet tile: the coefficient blocks of one shapelet and the
+// tile's visibility sums (one slot per thread and channel, FP64 on the mixed
+// paths; kept here rather than in registers, which the MFMA loop needs).
 template <int CM>
 struct ShpA {
-  float A[kA32PerShp];
+  float A[kPairsMax * kA32PerPair];
 };
 template <>
 struct ShpA<kCmBf16x2> {
-  uint4 A[kAbfPerShp / 8];
+  uint4 A[2 * kPairsMax * kAbfPerPair / 8];
 };
 template <>
 struct ShpA<kCmBf16x3> {
-  uint4 A[kAbfPerShp / 8];
+  uint4 A[3 * kPairsMax * kAbfPerPair / 8];
 };
-
-template <typename ACC, int CM = kCmF32>
-struct ShpSmem {
-  ACC acc_re[kShpChan][kTileRows], acc_im[kShpChan][kTileRows];
-  ShpA<CM> a;
-  double am[kTileRows], bm[kTileRows], t0[kTileRows];
+template <int CM>
+struct ShpSmem : ShpA<CM> {
+  double acc_re[kShpChan][kTileRows], acc_im[kShpChan][kTileRows];
 };
 
 // Per (visibility, shapelet) start value and phasor.  The synthetic envelopes
@@ -486,35 +486,128 @@ __device__ __forceinline__ float shp_phi0<float>(float x) {
   return (float)kPiM14 * __builtin_amdgcn_exp2f(-x * x * (float)kHalfLog2e);
 }
 
+// Exchange between the two halves of a wave (v_permlane32_swap).  Every lane
+// passes (p, q); afterwards lanes 0-31 hold (their own p, the p of lane + 32)
+// and lanes 32-63 hold (the q of lane - 32, their own q).  When p is the value
+// the lower half needs from a lane's visibility and q the one the upper half
+// needs, p ends up as the value for the lower half's visibility and q as the
+// value for the upper half's visibility, in every lane.
+__device__ __forceinline__ void half_swap(float &p, float &q) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(p), __float_as_uint(q), false, false);
+  p = __uint_as_float(r[0]);
+  q = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void half_swap(double &p, double &q) {
+  const uint64_t pu = (uint64_t)__double_as_longlong(p), qu = (uint64_t)__double_as_longlong(q);
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)pu, (uint32_t)qu, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(pu >> 32), (uint32_t)(qu >> 32), false, false);
+  p = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+  q = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+
+template <int CM>
+__device__ __forceinline__ floatx16 bf16_products(bf16x8 ah, bf16x8 am, bf16x8 al, bf16x8 bh, bf16x8 bm,
+                                                  bf16x8 bl) {
+  const floatx16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  floatx16 d;
+  // smallest products first
+  if (CM == kCmBf16x3) {
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, z, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, d, 0, 0, 0);
+  } else {
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, z, 0, 0, 0);
+  }
+  d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, d, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, d, 0, 0, 0);
+}
+
+// Fold one 32 x 32 block's FP32 accumulators into the DOT-precision sums:
+// walk the first-axis recurrence over the block's rows n0 + 8 g + r (this
+// lane's visibility), 8 rows at a time, bring each row value to the lanes
+// whose accumulator holds that row (half_swap) and add value x accumulator.
+// Accumulator register i of a lane in half h holds block row
+// 8 (i / 4) + 4 h + i % 4, of parity i % 2; even-n2 accumulators (E) pair
+// with even rows for the real part.  Only the first ng 8-row groups are
+// walked and folded (the rest of the block lies outside the triangle); with
+// ng = 4, (prev, cur) leave as the next block's start values.
+template <typename REC, typename DOT>
+__device__ __forceinline__ void shp_fold(REC x, REC &prev, REC &cur, int n0, int ng, const floatx16 &E0,
+                                         const floatx16 &O0, const floatx16 &E1, const floatx16 &O1, DOT &xr0,
+                                         DOT &xi0, DOT &xr1, DOT &xi1) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    if (g < ng) {
+    REC ra[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      ra[r] = cur;
+      const REC nx = herm_next<REC>(x, cur, prev, n0 + 8 * g + r);
+      prev = cur;
+      cur = nx;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * g + r;
+      DOT p0 = (DOT)ra[r], p1 = (DOT)ra[4 + r];
+      half_swap(p0, p1);
+      const DOT e0 = (DOT)E0[i], o0 = (DOT)O0[i], e1 = (DOT)E1[i], o1 = (DOT)O1[i];
+      if ((i & 1) == 0) {
+        xr0 = fma(p0, e0, xr0);
+        xi0 = fma(p0, o0, xi0);
+        xr1 = fma(p1, e1, xr1);
+        xi1 = fma(p1, o1, xi1);
+      } else {
+        xr0 = fma(p0, o0, xr0);
+        xi0 = fma(p0, e0, xi0);
+        xr1 = fma(p1, o1, xr1);
+        xi1 = fma(p1, e1, xi1);
+      }
+    }
+    }
+    // keep the 8-row groups in order: hoisting the recurrence ahead of the
+    // folds would hold all 32 of the block's values
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // One tile: kTileRows rows x kShpChan channels starting at channel block cb.
-// Each wave owns 64 rows; a group of 32 visibilities (32 rows of one channel)
-// is the N dimension of the MFMA, lanes l and l + 32 holding the two K
-// halves.  REC is the recurrence type, DOT the envelope accumulator type.
+// Lane l of wave w owns row 64 w + l and runs both Hermite recurrences of its
+// visibility (REC: FP64 on the mixed paths).  The MFMA's N dimension is 32
+// visibilities: group 0 is the lower half-wave's, group 1 the upper's, and
+// each operand value reaches the lane that supplies it through one half_swap
+// per pair of values.  M is a 32-row block of the first axis, K runs over the
+// second axis's orders with even orders in one accumulator and odd orders in
+// the other; after each 32 x 32 coefficient block the FP32 accumulators are
+// folded into a DOT-precision dot product with the first axis's values.  The
+// second axis is walked once per (visibility, channel); the first axis's
+// block values are recomputed per chunk from saved start values.
 template <typename REC, typename DOT, int CM = kCmF32>
-__device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpSmem<DOT, CM> &sm) {
+__device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpSmem<CM> &sm) {
   constexpr int KB = kShpChan;
+  constexpr int parts = CM == kCmBf16x3 ? 3 : 2;
   const int k0 = cb * KB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int h = lane >> 5, vv = lane & 31;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int64_t row = (int64_t)rb * kTileRows + tid;
   const bool valid = row < a.nrows;
   const int64_t rowc = valid ? row : a.nrows - 1;
-  const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
   const int K = a.K;
 
-  // accumulators start from what the point/Gaussian pass left
+  // sums start from what the point/Gaussian pass left
+#pragma unroll
   for (int c = 0; c < KB; ++c) {
-    DOT sr = 0, si = 0;
+    double sr = 0, si = 0;
     if (valid && k0 + c < K) {
       const int64_t idx = row * K + k0 + c;
       if (a.c64) {
         const float2 x = ((const float2 *)a.vis)[idx];
-        sr = (DOT)x.x;
-        si = (DOT)(a.conj ? -x.y : x.y);
+        sr = x.x;
+        si = a.conj ? -x.y : x.y;
       } else {
         const double2 x = ((const double2 *)a.vis)[idx];
-        sr = (DOT)x.x;
-        si = (DOT)(a.conj ? -x.y : x.y);
+        sr = x.x;
+        si = a.conj ? -x.y : x.y;
       }
     }
     sm.acc_re[c][tid] = sr;
@@ -525,28 +618,24 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
   const floatx16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int j = 0; j < a.S; ++j) {
     const int N = a.t.nmax[j];
-    const int MB = (N + 32) / 32, S4 = (N + 4) / 4;
-    const int NC = (N / 2 + 1 + 15) / 16;  // BF16 K steps (16 orders of one parity) per parity
-    __syncthreads();
-    {
-      if (CM == kCmF32) {
-        const float *src = a.t.a32 + a.t.a32_off[j];
-        const int n32 = MB * 2 * S4 * 64;
-        float *dst = (float *)&sm.a.A[0];
-        for (int i = tid; i < n32; i += kTileRows) dst[i] = src[i];
-      } else {
-        // hi, mid (and lo) parts, each MB * 2 * NC * 64 * 8 BF16 values
-        const int nbf = MB * 2 * NC * 64 * 8;
-        const int parts = CM == kCmBf16x3 ? 3 : 2;
-        const uint4 *src = (const uint4 *)(a.t.abf + a.t.abf_off[j]);
-        uint4 *dst = (uint4 *)&sm.a.A[0];
-        for (int i = tid; i < parts * nbf / 8; i += kTileRows) dst[i] = src[i];
-      }
-      const double *fr = a.d.sframe + 12 * j;
-      sm.am[tid] = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
-      sm.bm[tid] = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
-      sm.t0[tid] = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
+    const int q = N / 32;
+    const int npairs = (q + 1) * (q + 2) / 2;
+    __syncthreads();  // the previous shapelet's blocks are no longer read
+    if constexpr (CM == kCmF32) {
+      const uint4 *src = (const uint4 *)(a.t.a32 + a.t.a32_off[j]);
+      uint4 *dst = (uint4 *)&sm.A[0];
+      for (int i = tid; i < npairs * kA32PerPair / 4; i += kTileRows) dst[i] = src[i];
+    } else {
+      // the first `parts` split parts; each part holds npairs blocks
+      const uint4 *src = (const uint4 *)(a.t.abf + a.t.abf_off[j]);
+      uint4 *dst = &sm.A[0];
+      for (int i = tid; i < parts * npairs * kAbfPerPair / 8; i += kTileRows) dst[i] = src[i];
     }
+    const double *fr = a.d.sframe + 12 * j;
+    const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
+    const double am = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
+    const double bm = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
+    const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
     __syncthreads();
     const int jg = a.P + a.G + j;
     for (int c = 0; c < KB; ++c) {
@@ -554,187 +643,176 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
       const double f = a.fk[k0 + c];
       const DOT S = sizeof(DOT) == 8 ? (DOT)a.d.flux64[(int64_t)jg * a.Kpad + k0 + c]
                                      : (DOT)a.d.flux32[(int64_t)jg * a.Kpad + k0 + c];
+      const REC xa = (REC)am * (REC)f;
+      const REC xb = (REC)bm * (REC)f;
+      REC pb_m1 = 0, pb_n = shp_phi0<REC>(xb);
+      // start values (phi_{32 mb - 1}, phi_{32 mb}) of the first axis's
+      // blocks (named registers: the block loop is not unrolled), filled in
+      // while chunk 0 walks every block
+      REC s0m = 0, s0n = shp_phi0<REC>(xa), s1m = 0, s1n = 0, s2m = 0, s2n = 0, s3m = 0, s3n = 0;
+      DOT xr0 = 0, xi0 = 0, xr1 = 0, xi1 = 0;  // partial sums for groups 0 and 1
+      int pbase = 0;
+      for (int ch = 0; ch <= q; ++ch) {
+        // second axis, this lane's visibility: orders 32 ch + t, in groups of
+        // 8; groups past N (last chunk only) are zero
+        float ob[32];
+        {
+          const int nb8 = min(4, (N - 32 * ch) / 8 + 1);
+          REC prev = pb_m1, cur = pb_n;
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int rl = wave * 64 + hh * 32 + vv;
-        const REC xa = (REC)sm.am[rl] * (REC)f;
-        const REC xb = (REC)sm.bm[rl] * (REC)f;
-        const REC sxa = (REC)1.41421356237309504880 * xa;
-        const REC sxb = (REC)1.41421356237309504880 * xb;
-        const REC pb0 = shp_phi0<REC>(xb);
-        REC pa_m1 = 0, pa_n = shp_phi0<REC>(xa);
-        DOT xr = 0, xi = 0;
-        for (int mb = 0; mb < MB; ++mb) {
-          // first axis: the 16 rows of this 32-row block held by this lane
-          // (MFMA output row 8 (i/4) + 4 h + i % 4)
-          DOT pa[16];
+          for (int g = 0; g < 4; ++g) {
+            if (g < nb8) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            // named registers, not an array: a lane-dependent pick from an
-            // array becomes an indexed scratch access
-            const int n = 32 * mb + 8 * q;
-            const REC r0 = pa_n;
-            const REC r1 = herm_step<REC>(sxa, r0, pa_m1, n);
-            const REC r2 = herm_step<REC>(sxa, r1, r0, n + 1);
-            const REC r3 = herm_step<REC>(sxa, r2, r1, n + 2);
-            const REC r4 = herm_step<REC>(sxa, r3, r2, n + 3);
-            const REC r5 = herm_step<REC>(sxa, r4, r3, n + 4);
-            const REC r6 = herm_step<REC>(sxa, r5, r4, n + 5);
-            const REC r7 = herm_step<REC>(sxa, r6, r5, n + 6);
-            const REC r8 = herm_step<REC>(sxa, r7, r6, n + 7);
-            pa_m1 = r7;
-            pa_n = r8;
-            pa[4 * q + 0] = (DOT)(h ? r4 : r0);
-            pa[4 * q + 1] = (DOT)(h ? r5 : r1);
-            pa[4 * q + 2] = (DOT)(h ? r6 : r2);
-            pa[4 * q + 3] = (DOT)(h ? r7 : r3);
+              for (int t = 8 * g; t < 8 * g + 8; ++t) {
+                ob[t] = (float)cur;
+                const REC nx = herm_next<REC>(xb, cur, prev, 32 * ch + t);
+                prev = cur;
+                cur = nx;
+              }
+            } else {
+#pragma unroll
+              for (int t = 8 * g; t < 8 * g + 8; ++t) ob[t] = 0.f;
+            }
           }
-          if (CM != kCmF32) {
-            // second axis in 32-order chunks: this lane's half of each chunk
-            // (orders 32 ch + 16 h + [0, 16)) split into BF16 parts, even
-            // orders feeding the real and odd orders the imaginary accumulator
-            const int nbf = MB * 2 * NC * 64 * 8;
-            const __bf16 *Ab = (const __bf16 *)&sm.a.A[0];
-            const int chmax = (N - 32 * mb) / 32 + 1;
-            REC pb_m1 = 0, pb_n = pb0;
-            for (int ch = 0; ch < chmax; ++ch) {
-              float lo16[16], hi16[16];
-              REC q_prev = pb_m1, q_cur = pb_n;
+          pb_m1 = prev;
+          pb_n = cur;
+        }
+        // B operands of both groups.  FP32 MFMA (K = 2): lanes of half h
+        // supply orders 4 s + 2 h + parity of K step s, stored at [2 s + parity].
+        // BF16 MFMA (K = 16): lanes of half h supply orders 16 h + 2 e + parity,
+        // stored at [2 e + parity].
+        float bg0[16], bg1[16];
 #pragma unroll
-              for (int t = 0; t < 32; ++t) {
-                const REC q_next = herm_step<REC>(sxb, q_cur, q_prev, 32 * ch + t);
-                if (t < 16)
-                  lo16[t] = (float)q_cur;
-                else
-                  hi16[t - 16] = (float)q_cur;
-                q_prev = q_cur;
-                q_cur = q_next;
-              }
-              pb_m1 = q_prev;
-              pb_n = q_cur;
-              bf16x8 eh, em, el, oh, om, ol;
+        for (int t = 0; t < 16; ++t) {
+          const int lo = CM == kCmF32 ? 4 * (t >> 1) + (t & 1) : t;
+          const int hi = CM == kCmF32 ? lo + 2 : t + 16;
+          float p = ob[lo], qv = ob[hi];
+          half_swap(p, qv);
+          bg0[t] = p;
+          bg1[t] = qv;
+        }
+        bf16x8 Bh[2][2], Bm[2][2], Bl[2][2];  // [group][parity]
+        if (CM != kCmF32) {
+          // x = hi + mid + lo, each part rounded to nearest; two values per
+          // conversion instruction
 #pragma unroll
-              for (int e = 0; e < 8; ++e) {
-                const float ve = h ? hi16[2 * e] : lo16[2 * e];
-                const float vo = h ? hi16[2 * e + 1] : lo16[2 * e + 1];
-                eh[e] = (__bf16)ve;
-                oh[e] = (__bf16)vo;
-                const float re = ve - (float)eh[e], ro = vo - (float)oh[e];
-                em[e] = (__bf16)re;
-                om[e] = (__bf16)ro;
-                el[e] = (__bf16)(re - (float)em[e]);
-                ol[e] = (__bf16)(ro - (float)om[e]);
-              }
-              const int be_off = (((mb * 2 + 0) * NC + ch) * 64 + lane) * 8;
-              const int bo_off = (((mb * 2 + 1) * NC + ch) * 64 + lane) * 8;
-              const bf16x8 Aeh = *(const bf16x8 *)(Ab + be_off), Aoh = *(const bf16x8 *)(Ab + bo_off);
-              const bf16x8 Aem = *(const bf16x8 *)(Ab + nbf + be_off), Aom = *(const bf16x8 *)(Ab + nbf + bo_off);
-              floatx16 De, Do;
-              // smallest products first
-              if (CM == kCmBf16x3) {
-                const bf16x8 Ael = *(const bf16x8 *)(Ab + 2 * nbf + be_off);
-                const bf16x8 Aol = *(const bf16x8 *)(Ab + 2 * nbf + bo_off);
-                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aem, em, zero16, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aom, om, zero16, 0, 0, 0);
-                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ael, eh, De, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aol, oh, Do, 0, 0, 0);
-                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aeh, el, De, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aoh, ol, Do, 0, 0, 0);
-                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aem, eh, De, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aom, oh, Do, 0, 0, 0);
-              } else {
-                De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aem, eh, zero16, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aom, oh, zero16, 0, 0, 0);
-              }
-              De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aeh, em, De, 0, 0, 0);
-              Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aoh, om, Do, 0, 0, 0);
-              De = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aeh, eh, De, 0, 0, 0);
-              Do = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Aoh, oh, Do, 0, 0, 0);
+          for (int g = 0; g < 2; ++g)
 #pragma unroll
-              for (int i = 0; i < 16; ++i) {
-                const DOT te = (DOT)De[i], to = (DOT)Do[i];
-                if ((i & 1) == 0) {
-                  xr = fma(pa[i], te, xr);
-                  xi = fma(pa[i], to, xi);
-                } else {
-                  xr = fma(pa[i], to, xr);
-                  xi = fma(pa[i], te, xi);
+            for (int par = 0; par < 2; ++par)
+#pragma unroll
+              for (int e = 0; e < 8; e += 2) {
+                const float2v x = {g ? bg1[2 * e + par] : bg0[2 * e + par],
+                                   g ? bg1[2 * e + 2 + par] : bg0[2 * e + 2 + par]};
+                const bf16x2v h = __builtin_convertvector(x, bf16x2v);
+                const float2v r = x - __builtin_convertvector(h, float2v);
+                const bf16x2v m = __builtin_convertvector(r, bf16x2v);
+                const bf16x2v l = __builtin_convertvector(r - __builtin_convertvector(m, float2v), bf16x2v);
+                Bh[g][par][e] = h[0];
+                Bh[g][par][e + 1] = h[1];
+                Bm[g][par][e] = m[0];
+                Bm[g][par][e + 1] = m[1];
+                Bl[g][par][e] = l[0];
+                Bl[g][par][e + 1] = l[1];
+              }
+        }
+        const int nmb = q - ch + 1;
+        for (int mb = 0; mb < nmb; ++mb) {
+          const int p = pbase + mb;
+          // first axis, this lane's visibility: rows 32 mb + 8 g + r, walked
+          // 8 rows at a time and folded as they come.  Accumulator register
+          // i of a lane in half h holds block row 8 (i / 4) + 4 h + i % 4, of
+          // parity i % 2.
+          REC prev = mb == 0 ? s0m : mb == 1 ? s1m : mb == 2 ? s2m : s3m;
+          REC cur = mb == 0 ? s0n : mb == 1 ? s1n : mb == 2 ? s2n : s3n;
+          // 8-row groups of this block that meet the triangle; all four while
+          // chunk 0 walks towards a further block's start values
+          const int ng = (ch == 0 && mb < q) ? 4 : min(4, (N - 32 * (ch + mb)) / 8 + 1);
+          if constexpr (CM == kCmF32) {
+            // K steps of this block inside the triangle: 32 (ch + mb) + 4 s <= N,
+            // in two halves of 4 steps, each folded as soon as it is summed
+            // (an FP32 sum over all 8 steps loses ~1.5x more to the
+            // coefficients' cancellation); the second fold walks the rows again
+            const int smax = min(8, (N - 32 * (ch + mb)) / 4 + 1);
+            const float *Ap = &sm.A[p * kA32PerPair];
+            const REC prev0 = prev, cur0 = cur;
+            const int nh = smax > 4 ? 2 : 1;
+#pragma nounroll
+            for (int hf = 0; hf < nh; ++hf) {
+              floatx16 E0 = zero16, O0 = zero16, E1 = zero16, O1 = zero16;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int st = 4 * hf + k;
+                if (st < smax) {
+                  const float ae = Ap[st * 64 + lane], ao = Ap[(8 + st) * 64 + lane];
+                  const float b0e = hf ? bg0[8 + 2 * k] : bg0[2 * k], b0o = hf ? bg0[9 + 2 * k] : bg0[2 * k + 1];
+                  const float b1e = hf ? bg1[8 + 2 * k] : bg1[2 * k], b1o = hf ? bg1[9 + 2 * k] : bg1[2 * k + 1];
+                  E0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, b0e, E0, 0, 0, 0);
+                  O0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, b0o, O0, 0, 0, 0);
+                  E1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, b1e, E1, 0, 0, 0);
+                  O1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, b1o, O1, 0, 0, 0);
                 }
               }
+              prev = prev0;
+              cur = cur0;
+              shp_fold<REC, DOT>(xa, prev, cur, 32 * mb, ng, E0, O0, E1, O1, xr0, xi0, xr1, xi1);
             }
-            continue;
+          } else {
+            const __bf16 *Ab = (const __bf16 *)&sm.A[0];
+            const int part = npairs * kAbfPerPair;
+            const int oe = p * kAbfPerPair + lane * 8, oo = oe + 64 * 8;
+            const bf16x8 Aeh = *(const bf16x8 *)(Ab + oe), Aoh = *(const bf16x8 *)(Ab + oo);
+            const bf16x8 Aem = *(const bf16x8 *)(Ab + part + oe), Aom = *(const bf16x8 *)(Ab + part + oo);
+            bf16x8 Ael = Aem, Aol = Aom;
+            if (CM == kCmBf16x3) {
+              Ael = *(const bf16x8 *)(Ab + 2 * part + oe);
+              Aol = *(const bf16x8 *)(Ab + 2 * part + oo);
+            }
+            const floatx16 E0 = bf16_products<CM>(Aeh, Aem, Ael, Bh[0][0], Bm[0][0], Bl[0][0]);
+            const floatx16 O0 = bf16_products<CM>(Aoh, Aom, Aol, Bh[0][1], Bm[0][1], Bl[0][1]);
+            const floatx16 E1 = bf16_products<CM>(Aeh, Aem, Ael, Bh[1][0], Bm[1][0], Bl[1][0]);
+            const floatx16 O1 = bf16_products<CM>(Aoh, Aom, Aol, Bh[1][1], Bm[1][1], Bl[1][1]);
+            shp_fold<REC, DOT>(xa, prev, cur, 32 * mb, ng, E0, O0, E1, O1, xr0, xi0, xr1, xi1);
           }
-          // second axis: recurrence feeding the B operand, K restricted to the
-          // triangle n1 + n2 <= N of this block
-          const float *A32 = (const float *)&sm.a.A[0];
-          const int smax = (N - 32 * mb) / 4 + 1;
-          REC pb_m1 = 0, pb_n = pb0;
-          floatx16 De = zero16, Do = zero16;
-          for (int s0 = 0; s0 < smax; s0 += kFoldSteps) {
-#pragma unroll
-            for (int uu = 0; uu < kFoldSteps; ++uu) {
-              const int s4 = s0 + uu;
-              if (s4 < smax) {
-                const int n = 4 * s4;
-                const REC q0 = pb_n;
-                const REC q1 = herm_step<REC>(sxb, q0, pb_m1, n);
-                const REC q2 = herm_step<REC>(sxb, q1, q0, n + 1);
-                const REC q3 = herm_step<REC>(sxb, q2, q1, n + 2);
-                const REC q4 = herm_step<REC>(sxb, q3, q2, n + 3);
-                pb_m1 = q3;
-                pb_n = q4;
-                const float be = (float)(h ? q2 : q0);
-                const float bo = (float)(h ? q3 : q1);
-                const int ie = ((mb * 2 + 0) * S4 + s4) * 64 + lane;
-                const int io = ((mb * 2 + 1) * S4 + s4) * 64 + lane;
-                De = __builtin_amdgcn_mfma_f32_32x32x2f32(A32[ie], be, uu == 0 ? zero16 : De, 0, 0, 0);
-                Do = __builtin_amdgcn_mfma_f32_32x32x2f32(A32[io], bo, uu == 0 ? zero16 : Do, 0, 0, 0);
-              }
-            }
-            // fold: xi += sum over this lane's rows of phi_n1(a) * T[n1]
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-              const DOT te = (DOT)De[i], to = (DOT)Do[i];
-              if ((i & 1) == 0) {
-                xr = fma(pa[i], te, xr);
-                xi = fma(pa[i], to, xi);
-              } else {
-                xr = fma(pa[i], to, xr);
-                xi = fma(pa[i], te, xi);
-              }
-            }
+          if (ch == 0) {
+            s1m = mb == 0 ? prev : s1m;
+            s1n = mb == 0 ? cur : s1n;
+            s2m = mb == 1 ? prev : s2m;
+            s2n = mb == 1 ? cur : s2n;
+            s3m = mb == 2 ? prev : s3m;
+            s3n = mb == 2 ? cur : s3n;
           }
         }
-        xr += __shfl_xor(xr, 32);
-        xi += __shfl_xor(xi, 32);
-        // phase, flux and accumulation
-        DOT cs, sn;
-        if (sizeof(DOT) == 8) {
-          double c8, s8;
-          turns_sincos_f64(sm.t0[rl] * f, c8, s8);
-          cs = (DOT)c8;
-          sn = (DOT)s8;
-        } else {
-          float c4, s4;
-          turns_sincos_f32((float)sm.t0[rl] * (float)f, c4, s4);
-          cs = (DOT)c4;
-          sn = (DOT)s4;
-        }
-        const DOT tr = sgn * S * (xr * cs - xi * sn);
-        const DOT ti = sgn * S * (xr * sn + xi * cs);
-        if (h == hh) {
-          sm.acc_re[c][rl] += tr;
-          sm.acc_im[c][rl] += ti;
-        }
+        pbase += nmb;
       }
+      // each group's two half-wave partial sums, brought to the owning lane
+      half_swap(xr0, xr1);
+      half_swap(xi0, xi1);
+      const DOT xr = xr0 + xr1, xi = xi0 + xi1;
+      // phase, flux and accumulation
+      DOT cs, sn;
+      if (sizeof(DOT) == 8) {
+        double c8, s8;
+        turns_sincos_f64(t0 * f, c8, s8);
+        cs = (DOT)c8;
+        sn = (DOT)s8;
+      } else {
+        float c4, s4;
+        turns_sincos_f32((float)t0 * (float)f, c4, s4);
+        cs = (DOT)c4;
+        sn = (DOT)s4;
+      }
+      const DOT tr = sgn * S * (xr * cs - xi * sn);
+      const DOT ti = sgn * S * (xr * sn + xi * cs);
+      sm.acc_re[c][tid] = (double)((DOT)sm.acc_re[c][tid] + tr);
+      sm.acc_im[c][tid] = (double)((DOT)sm.acc_im[c][tid] + ti);
     }
   }
-  __syncthreads();
   if (!valid) return;
+#pragma unroll
   for (int c = 0; c < KB; ++c) {
     if (k0 + c >= K) break;
     const int64_t idx = row * K + k0 + c;
-    const double re = (double)sm.acc_re[c][tid], im = (double)sm.acc_im[c][tid];
+    const double re = sm.acc_re[c][tid], im = sm.acc_im[c][tid];
     if (a.c64)
       ((float2 *)a.vis)[idx] = make_float2((float)re, (float)(a.conj ? -im : im));
     else
@@ -743,8 +821,8 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
 }
 
 template <typename REC, typename DOT, int CM>
-__global__ __launch_bounds__(kTileRows) void k_shp_mfma(TileArgs a) {
-  __shared__ ShpSmem<DOT, CM> sm;
+__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_shp_mfma(TileArgs a) {
+  __shared__ ShpSmem<CM> sm;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   shp_tile<REC, DOT, CM>(a, tile % a.n_rb, tile / a.n_rb, sm);
 }
@@ -888,10 +966,10 @@ __device__ __noinline__ void serve_table_item(const ServeJobDesc &job, int64_t i
 
 union ServeSmem {
   PgSmem<float> pg;
-  ShpSmem<double> shp;
+  ShpSmem<kCmF32> shp;
 };
 
-__global__ __launch_bounds__(kTileRows) void k_serve(ServeHost *H, ServeDev *D, uint64_t idle_ticks,
+__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_serve(ServeHost *H, ServeDev *D, uint64_t idle_ticks,
                                                      uint64_t epoch) {
   __shared__ ServeSmem sm;
   __shared__ ServeJobDesc job;
@@ -1029,14 +1107,20 @@ static hipError_t upload_tables() {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
-  double sq[128], isq[128];
+  double sq[128], isq[128], ab[128][2];
+  float ab32[128][2];
   for (int n = 0; n < 128; ++n) {
     sq[n] = sqrt((double)n);
     isq[n] = 1.0 / sqrt((double)n + 1.0);
+    ab[n][0] = sqrt(2.0 / ((double)n + 1.0));
+    ab[n][1] = sqrt((double)n / ((double)n + 1.0));
+    ab32[n][0] = (float)ab[n][0];
+    ab32[n][1] = (float)ab[n][1];
   }
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_sqn), sq, sizeof(sq));
-  if (e != hipSuccess) return e;
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_isqn1), isq, sizeof(isq));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_isqn1), isq, sizeof(isq));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_ab64), ab, sizeof(ab));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_ab32), ab32, sizeof(ab32));
   if (e == hipSuccess && dev >= 0 && dev < 64) done[dev] = true;
   return e;
 }
