@@ -93,8 +93,8 @@ def shapelet_contraction(reps=5, check_rows=48):
     ref = oracle.predict(obs, sky, rows=rows)
     res = {"workload": synth.CONFIG_NAMES[2], "n_vis": obs.n_vis, "nmax": [int(n) for n in sky.s_nmax],
            "algorithmic_flops_per_launch": alg_flops, "modes": {}}
-    for name, prec, mode, peak in (("mixed_fp32_mfma", vp.VP_PREC_MIXED, "f32", MFMA_PEAK_F32),
-                                   ("mixed_bf16x3", vp.VP_PREC_MIXED_BF16, "bf16x3", MFMA_PEAK_BF16)):
+    for name, prec, mode, peak in (("mixed_bf16x3", vp.VP_PREC_MIXED, "bf16x3", MFMA_PEAK_BF16),
+                                   ("mixed_f32mma", vp.VP_PREC_MIXED_F32MMA, "f32", MFMA_PEAK_F32)):
         vp.vp_predict(ctx, sh, oh, prec, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
         torch.cuda.synchronize()
         vp.vp_profile(ctx, True)

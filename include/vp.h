@@ -63,10 +63,14 @@ extern "C" {
 /* precision paths */
 #define VP_PREC_FP64 0        /* FP64 everywhere (phase, sincos, envelopes, recurrence, contraction, sums) */
 #define VP_PREC_MIXED 1       /* FP64 phase + range reduction; FP32 sincos/envelopes/Kahan sums;
-                                 FP64 Hermite recurrence; FP32 MFMA shapelet contraction */
-#define VP_PREC_MIXED_BF16 2  /* as MIXED, contraction as 3-way BF16 split on MFMA (6 products) */
+                                 FP64 Hermite recurrence; shapelet contraction on MFMA with the
+                                 coefficients and Hermite values split into 3 BF16 parts (6 products,
+                                 FP32 accumulation, folded into FP64 per 32 orders) */
+#define VP_PREC_MIXED_BF16 2  /* the same path as VP_PREC_MIXED (explicit name of its contraction) */
 #define VP_PREC_FP32 3        /* FP32 everywhere, phase included (reported, not accurate) */
-#define VP_PREC_MIXED_BF16X2 4 /* as MIXED, contraction as 2-way BF16 split (3 products) */
+#define VP_PREC_MIXED_BF16X2 4 /* as MIXED, contraction as 2-way BF16 split (3 products; reported) */
+#define VP_PREC_MIXED_F32MMA 5 /* as MIXED, contraction on FP32 MFMA folded into FP64 every 8 orders
+                                  (reported: ~1e-6 of total flux on heavily cancelling coefficients) */
 
 /* output element types */
 #define VP_C128 0

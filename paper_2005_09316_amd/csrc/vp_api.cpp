@@ -294,7 +294,7 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
 int check_call(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis) {
   if (!ctx || !sky || !obs) return set_error(VP_EINVAL, "NULL context, sky or observation");
   if (sky->ctx != ctx || obs->ctx != ctx) return set_error(VP_EINVAL, "sky or observation belongs to another context");
-  if (precision < VP_PREC_FP64 || precision > VP_PREC_MIXED_BF16X2)
+  if (precision < VP_PREC_FP64 || precision > VP_PREC_MIXED_F32MMA)
     return set_error(VP_EINVAL, "unknown precision %d", precision);
   if (dtype != VP_C128 && dtype != VP_C64) return set_error(VP_EINVAL, "unknown dtype %d", dtype);
   if (!vis) return set_error(VP_EINVAL, "NULL visibility buffer");

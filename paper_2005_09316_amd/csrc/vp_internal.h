@@ -32,7 +32,7 @@ constexpr int kPairsMax = (kNmaxLimit / 32 + 1) * (kNmaxLimit / 32 + 2) / 2;
 constexpr int kA32PerPair = 2 * 8 * 64;  // floats: [parity][K step of 2 orders][lane]
 constexpr int kAbfPerPair = 2 * 64 * 8;  // BF16 values of one split part: [parity][lane][8]
 
-enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4 };
+enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4, kMixedF32Mma = 5 };
 
 // Per-(sky, observation) tables, built on the device.  Plain aggregates (no
 // member initialisers) so that they can live in LDS inside the serving kernel.

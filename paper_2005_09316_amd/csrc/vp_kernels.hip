@@ -41,8 +41,10 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __constant__ double c_sqn[128];   // sqrt(n)
 __constant__ double c_isqn1[128]; // 1 / sqrt(n + 1)
-__constant__ double c_ab64[128][2]; // (sqrt(2 / (n + 1)), sqrt(n / (n + 1)))
-__constant__ float c_ab32[128][2];  // the same, rounded to FP32
+__constant__ double c_half[128];   // n / 2
+// scales of the rescaled Hermite values (see shp_tile): [0] = s_16 / s_0,
+// [k] = s_{32k+16} / s_{32k-16} for k = 1, 2, 3, with s_n = sqrt(2^n / n!)
+__constant__ double c_sc[4];
 
 static constexpr double kPiM14 = 0.75112554446494248285870300477622; // pi^(-1/4)
 static constexpr double kHalfLog2e = 0.72134752044448170367996234050095; // log2(e) / 2
@@ -183,6 +185,18 @@ __global__ void k_flux(FluxArgs a) {
 //        32x32x16 MFMA, element e of lane l: n1 = 32 mb + l % 32,
 //        n2 = 32 ch + 16 (l / 32) + 2 e + parity;
 //   c64: [n1][ld], zero outside the triangle.
+// The MFMA tiles hold C'' (s_n1 / s_{32 mb + 16}) (s_n2 / s_{32 ch + 16}): the
+// kernels walk the rescaled Hermite values of psi_next (FP64 bases at the
+// middle of each block), and these factors undo the rescaling.
+
+// s_n / s_b with s_n = sqrt(2^n / n!), as a product of sqrt(2 / (k + 1)).
+__host__ __device__ inline double herm_scale(int b, int n) {
+  double r = 1.0;
+  for (int k = b; k < n; ++k) r *= sqrt(2.0 / (k + 1));
+  for (int k = n; k < b; ++k) r /= sqrt(2.0 / (k + 1));
+  return r;
+}
+
 __device__ __forceinline__ double signed_coeff(const double *c, int N, int n1, int n2) {
   if (n1 < 0 || n2 < 0 || n1 > N || n2 > N - n1) return 0.0;
   const int64_t off = (int64_t)n1 * (N + 1) - (int64_t)n1 * (n1 - 1) / 2;
@@ -221,7 +235,9 @@ __global__ void k_tiles(TileBuildArgs a) {
     int ch, mb;
     pair_coords(q, p, ch, mb);
     const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 4 * st + 2 * (lane >> 5) + par;
-    a.a32[a.a32_off[s] + i] = (float)signed_coeff(C, N, n1, n2);
+    const double v = signed_coeff(C, N, n1, n2);
+    a.a32[a.a32_off[s] + i] =
+        v == 0.0 ? 0.f : (float)(v * herm_scale(32 * mb + 16, n1) * herm_scale(32 * ch + 16, n2));
   }
   // FP64 dense
   const int ld = a.c64_ld[s];
@@ -236,7 +252,8 @@ __global__ void k_tiles(TileBuildArgs a) {
     int ch, mb;
     pair_coords(q, p, ch, mb);
     const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 16 * (lane >> 5) + 2 * e + par;
-    const float x = (float)signed_coeff(C, N, n1, n2);
+    const double v = signed_coeff(C, N, n1, n2);
+    const float x = v == 0.0 ? 0.f : (float)(v * herm_scale(32 * mb + 16, n1) * herm_scale(32 * ch + 16, n2));
     const uint16_t hi = bf16_rne(x);
     const float r1 = x - bf16_to_f(hi);
     const uint16_t mid = bf16_rne(r1);
@@ -426,19 +443,15 @@ __device__ __forceinline__ R herm_step(R sx, R pn, R pm1, int n) {
   return (R)c_isqn1[n] * fma(sx, pn, -(R)c_sqn[n] * pm1);
 }
 
-// The same recurrence as phi_{n+1} = alpha_n x phi_n - beta_n phi_{n-1} with
-// alpha_n = sqrt(2 / (n + 1)) and beta_n = sqrt(n / (n + 1)): both products
-// with the constants are independent of phi_n, so one FMA per order sits on
-// the dependency chain.
+// Rescaled Hermite functions.  With s_n = sqrt(2^n / n!) and a base order b,
+// u_n = phi_n s_b / s_n obeys u_{n+1} = x u_n - (n / 2) u_{n-1}: two
+// operations per order and a constant that is a short immediate (n / 2 is a
+// half-integer).  The MFMA path walks u with b at the middle of each 32-order
+// block (|log10 (s_b / s_n)| <= 14 there) and multiplies the coefficient tiles
+// by (s_n1 / s_b1)(s_n2 / s_b2), so that the products are unchanged.
 template <typename R>
-__device__ __forceinline__ R herm_next(R x, R pn, R pm1, int n);
-template <>
-__device__ __forceinline__ double herm_next<double>(double x, double pn, double pm1, int n) {
-  return fma(c_ab64[n][0] * x, pn, -c_ab64[n][1] * pm1);
-}
-template <>
-__device__ __forceinline__ float herm_next<float>(float x, float pn, float pm1, int n) {
-  return fmaf(c_ab32[n][0] * x, pn, -c_ab32[n][1] * pm1);
+__device__ __forceinline__ R psi_next(R x, R un, R um1, R half_n) {
+  return fma(x, un, -half_n * um1);
 }
 
 // Contraction modes: FP32 MFMA, or the coefficients and the second axis's
@@ -524,8 +537,8 @@ __device__ __forceinline__ floatx16 bf16_products(bf16x8 ah, bf16x8 am, bf16x8 a
 }
 
 // Fold one 32 x 32 block's FP32 accumulators into the DOT-precision sums:
-// walk the first-axis recurrence over the block's rows n0 + 8 g + r (this
-// lane's visibility), 8 rows at a time, bring each row value to the lanes
+// walk the first-axis recurrence (rescaled, psi_next) over the block's rows
+// n0 + 8 g + r (this lane's visibility), 8 rows at a time, bring each row value to the lanes
 // whose accumulator holds that row (half_swap) and add value x accumulator.
 // Accumulator register i of a lane in half h holds block row
 // 8 (i / 4) + 4 h + i % 4, of parity i % 2; even-n2 accumulators (E) pair
@@ -543,7 +556,7 @@ __device__ __forceinline__ void shp_fold(REC x, REC &prev, REC &cur, int n0, int
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       ra[r] = cur;
-      const REC nx = herm_next<REC>(x, cur, prev, n0 + 8 * g + r);
+      const REC nx = psi_next<REC>(x, cur, prev, (REC)(0.5 * (n0 + 8 * g + r)));
       prev = cur;
       cur = nx;
     }
@@ -645,11 +658,19 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
                                      : (DOT)a.d.flux32[(int64_t)jg * a.Kpad + k0 + c];
       const REC xa = (REC)am * (REC)f;
       const REC xb = (REC)bm * (REC)f;
-      REC pb_m1 = 0, pb_n = shp_phi0<REC>(xb);
-      // start values (phi_{32 mb - 1}, phi_{32 mb}) of the first axis's
-      // blocks (named registers: the block loop is not unrolled), filled in
-      // while chunk 0 walks every block
-      REC s0m = 0, s0n = shp_phi0<REC>(xa), s1m = 0, s1n = 0, s2m = 0, s2n = 0, s3m = 0, s3n = 0;
+      // rescaled walks (psi_next): block or chunk k of 32 orders uses base
+      // order 32 k + 16; carried values are rescaled when the base moves
+      REC pb_m1 = 0, pb_n = shp_phi0<REC>(xb) * (REC)c_sc[0];
+      // start values (u_{32 mb - 1}, u_{32 mb}) of the first axis's blocks,
+      // filled in while chunk 0 walks every block
+      REC sam[kMBMax], san[kMBMax];
+      sam[0] = 0;
+      san[0] = shp_phi0<REC>(xa) * (REC)c_sc[0];
+#pragma unroll
+      for (int k = 1; k < kMBMax; ++k) {
+        sam[k] = 0;
+        san[k] = 0;
+      }
       DOT xr0 = 0, xi0 = 0, xr1 = 0, xi1 = 0;  // partial sums for groups 0 and 1
       int pbase = 0;
       for (int ch = 0; ch <= q; ++ch) {
@@ -665,7 +686,7 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
 #pragma unroll
               for (int t = 8 * g; t < 8 * g + 8; ++t) {
                 ob[t] = (float)cur;
-                const REC nx = herm_next<REC>(xb, cur, prev, 32 * ch + t);
+                const REC nx = psi_next<REC>(xb, cur, prev, (REC)c_half[32 * ch + t]);
                 prev = cur;
                 cur = nx;
               }
@@ -674,8 +695,10 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
               for (int t = 8 * g; t < 8 * g + 8; ++t) ob[t] = 0.f;
             }
           }
-          pb_m1 = prev;
-          pb_n = cur;
+          // next chunk's base
+          const REC rs = ch < 3 ? (REC)c_sc[ch + 1] : (REC)1;
+          pb_m1 = prev * rs;
+          pb_n = cur * rs;
         }
         // B operands of both groups.  FP32 MFMA (K = 2): lanes of half h
         // supply orders 4 s + 2 h + parity of K step s, stored at [2 s + parity].
@@ -716,14 +739,15 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
               }
         }
         const int nmb = q - ch + 1;
-        for (int mb = 0; mb < nmb; ++mb) {
+#pragma unroll
+        for (int mb = 0; mb < kMBMax; ++mb) {
+          if (mb >= nmb) break;
           const int p = pbase + mb;
           // first axis, this lane's visibility: rows 32 mb + 8 g + r, walked
           // 8 rows at a time and folded as they come.  Accumulator register
           // i of a lane in half h holds block row 8 (i / 4) + 4 h + i % 4, of
           // parity i % 2.
-          REC prev = mb == 0 ? s0m : mb == 1 ? s1m : mb == 2 ? s2m : s3m;
-          REC cur = mb == 0 ? s0n : mb == 1 ? s1n : mb == 2 ? s2n : s3n;
+          REC prev = sam[mb], cur = san[mb];
           // 8-row groups of this block that meet the triangle; all four while
           // chunk 0 walks towards a further block's start values
           const int ng = (ch == 0 && mb < q) ? 4 : min(4, (N - 32 * (ch + mb)) / 8 + 1);
@@ -773,13 +797,9 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
             const floatx16 O1 = bf16_products<CM>(Aoh, Aom, Aol, Bh[1][1], Bm[1][1], Bl[1][1]);
             shp_fold<REC, DOT>(xa, prev, cur, 32 * mb, ng, E0, O0, E1, O1, xr0, xi0, xr1, xi1);
           }
-          if (ch == 0) {
-            s1m = mb == 0 ? prev : s1m;
-            s1n = mb == 0 ? cur : s1n;
-            s2m = mb == 1 ? prev : s2m;
-            s2n = mb == 1 ? cur : s2n;
-            s3m = mb == 2 ? prev : s3m;
-            s3n = mb == 2 ? cur : s3n;
+          if (mb + 1 < kMBMax && ch == 0 && mb < q) {
+            sam[mb + 1] = prev * (REC)c_sc[mb + 1];
+            san[mb + 1] = cur * (REC)c_sc[mb + 1];
           }
         }
         pbase += nmb;
@@ -966,7 +986,7 @@ __device__ __noinline__ void serve_table_item(const ServeJobDesc &job, int64_t i
 
 union ServeSmem {
   PgSmem<float> pg;
-  ShpSmem<kCmF32> shp;
+  ShpSmem<kCmBf16x3> shp;
 };
 
 __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_serve(ServeHost *H, ServeDev *D, uint64_t idle_ticks,
@@ -1080,8 +1100,8 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
     pg_tile<kMixed>(job.a, rb, cb, sm.pg);
     __syncthreads();  // the tile's point/Gaussian sums are visible to the whole workgroup
     if (job.a.S > 0) {
-      shp_tile<double, double>(job.a, rb, 2 * cb, sm.shp);
-      shp_tile<double, double>(job.a, rb, 2 * cb + 1, sm.shp);
+      shp_tile<double, double, kCmBf16x3>(job.a, rb, 2 * cb, sm.shp);
+      shp_tile<double, double, kCmBf16x3>(job.a, rb, 2 * cb + 1, sm.shp);
     }
     __syncthreads();
     if (tid == 0) {
@@ -1107,20 +1127,18 @@ static hipError_t upload_tables() {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
-  double sq[128], isq[128], ab[128][2];
-  float ab32[128][2];
+  double sq[128], isq[128], half[128], sc[4];
   for (int n = 0; n < 128; ++n) {
     sq[n] = sqrt((double)n);
     isq[n] = 1.0 / sqrt((double)n + 1.0);
-    ab[n][0] = sqrt(2.0 / ((double)n + 1.0));
-    ab[n][1] = sqrt((double)n / ((double)n + 1.0));
-    ab32[n][0] = (float)ab[n][0];
-    ab32[n][1] = (float)ab[n][1];
+    half[n] = 0.5 * n;
   }
+  sc[0] = herm_scale(0, 16);
+  for (int k = 1; k < 4; ++k) sc[k] = herm_scale(32 * k - 16, 32 * k + 16);
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_sqn), sq, sizeof(sq));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_isqn1), isq, sizeof(isq));
-  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_ab64), ab, sizeof(ab));
-  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_ab32), ab32, sizeof(ab32));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_half), half, sizeof(half));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_sc), sc, sizeof(sc));
   if (e == hipSuccess && dev >= 0 && dev < 64) done[dev] = true;
   return e;
 }
@@ -1189,10 +1207,11 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) 
       hipLaunchKernelGGL((k_shp_mfma<float, float, kCmF32>), g, b, 0, s, a);
       break;
     case kMixed:
-      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmF32>), g, b, 0, s, a);
-      break;
     case kMixedBf16:
       hipLaunchKernelGGL((k_shp_mfma<double, double, kCmBf16x3>), g, b, 0, s, a);
+      break;
+    case kMixedF32Mma:
+      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmF32>), g, b, 0, s, a);
       break;
     case kMixedBf16x2:
       hipLaunchKernelGGL((k_shp_mfma<double, double, kCmBf16x2>), g, b, 0, s, a);

@@ -81,9 +81,9 @@ def test_predict_matches_oracle(ctx, name, prec, dtype):
 
 
 @pytest.mark.parametrize("name", ["tiny", "fornax-mid", "nmax-limit"])
-@pytest.mark.parametrize("prec", [vp.VP_PREC_FP32, vp.VP_PREC_MIXED_BF16X2])
+@pytest.mark.parametrize("prec", [vp.VP_PREC_FP32, vp.VP_PREC_MIXED_BF16X2, vp.VP_PREC_MIXED_F32MMA])
 def test_reported_paths(ctx, name, prec):
-    """FP32-only and 2-way BF16 paths: error reported, not gated."""
+    """FP32-only, 2-way BF16 and FP32-MFMA contraction paths: error reported, not gated."""
     obs, sky, ref = _ref(name)
     with Handles(ctx, obs, sky) as h:
         got = run(ctx, h.obs, h.sky, obs, prec, vp.VP_C64)
