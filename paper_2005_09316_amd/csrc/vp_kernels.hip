@@ -717,26 +717,47 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
         bf16x8 Bh[2][2], Bm[2][2], Bl[2][2];  // [group][parity]
         if (CM != kCmF32) {
           // x = hi + mid + lo, each part rounded to nearest; two values per
-          // conversion instruction
+          // conversion instruction.  Element e of either half carries order
+          // 16 h + 2 e + parity of the chunk: when fewer than 16 orders of the
+          // chunk are inside the triangle, elements past them are zero in
+          // both halves and are not split.
+          const int rch = N - 32 * ch;
+          const int ne = rch < 16 ? rch / 4 + 1 : 4;  // element pairs (e, e + 1) to split
 #pragma unroll
-          for (int g = 0; g < 2; ++g)
+          for (int e = 0; e < 8; e += 2) {
+            if (e / 2 < ne) {
 #pragma unroll
-            for (int par = 0; par < 2; ++par)
+              for (int g = 0; g < 2; ++g)
 #pragma unroll
-              for (int e = 0; e < 8; e += 2) {
-                const float2v x = {g ? bg1[2 * e + par] : bg0[2 * e + par],
-                                   g ? bg1[2 * e + 2 + par] : bg0[2 * e + 2 + par]};
-                const bf16x2v h = __builtin_convertvector(x, bf16x2v);
-                const float2v r = x - __builtin_convertvector(h, float2v);
-                const bf16x2v m = __builtin_convertvector(r, bf16x2v);
-                const bf16x2v l = __builtin_convertvector(r - __builtin_convertvector(m, float2v), bf16x2v);
-                Bh[g][par][e] = h[0];
-                Bh[g][par][e + 1] = h[1];
-                Bm[g][par][e] = m[0];
-                Bm[g][par][e + 1] = m[1];
-                Bl[g][par][e] = l[0];
-                Bl[g][par][e + 1] = l[1];
-              }
+                for (int par = 0; par < 2; ++par) {
+                  const float2v x = {g ? bg1[2 * e + par] : bg0[2 * e + par],
+                                     g ? bg1[2 * e + 2 + par] : bg0[2 * e + 2 + par]};
+                  const bf16x2v h = __builtin_convertvector(x, bf16x2v);
+                  const float2v r = x - __builtin_convertvector(h, float2v);
+                  const bf16x2v m = __builtin_convertvector(r, bf16x2v);
+                  const bf16x2v l = __builtin_convertvector(r - __builtin_convertvector(m, float2v), bf16x2v);
+                  Bh[g][par][e] = h[0];
+                  Bh[g][par][e + 1] = h[1];
+                  Bm[g][par][e] = m[0];
+                  Bm[g][par][e + 1] = m[1];
+                  Bl[g][par][e] = l[0];
+                  Bl[g][par][e + 1] = l[1];
+                }
+            } else {
+#pragma unroll
+              for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int par = 0; par < 2; ++par) {
+                  const __bf16 z = (__bf16)0.f;
+                  Bh[g][par][e] = z;
+                  Bh[g][par][e + 1] = z;
+                  Bm[g][par][e] = z;
+                  Bm[g][par][e + 1] = z;
+                  Bl[g][par][e] = z;
+                  Bl[g][par][e + 1] = z;
+                }
+            }
+          }
         }
         const int nmb = q - ch + 1;
 #pragma unroll
