@@ -19,7 +19,10 @@ The JSON line carries:
                   algorithmic contraction FLOP/s (2 p_tot per visibility and
                   shapelet) against the FP32 MFMA peak, and the MFMA work the
                   kernel issues against the peak of the instruction type used.
-                  `--only-shapelets` runs this leg alone (for profiling).
+                  `--only-shapelets` runs this leg alone (for profiling);
+  truncation_sweep -- the paper's model truncation (Sec. 5.3) on its peel
+                  observation: GPU time and error against the full model per
+                  fraction of components kept.
 """
 from __future__ import annotations
 
@@ -119,6 +122,84 @@ def shapelet_contraction(reps=5, check_rows=48):
         _log("shapelet kernel %s: %.3f ms, %.1f TFLOP/s algorithmic (%.1f%% of FP32 MFMA peak), "
              "err %.2e" % (name, ms, r["algorithmic_tflops"], 100 * r["frac_of_fp32_mfma_peak"], err))
     vp.vp_destroy_sky(sh)
+    vp.vp_destroy_obs(oh)
+    vp.vp_destroy_ctx(ctx)
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def truncation_sweep(check_rows=8, fracs=(1.0, 0.95, 0.9, 0.8, 0.7, 0.5), orders=(86, 78, 70, 63, 54, 40)):
+    """The paper's compute-vs-accuracy lever (Sec. 5.3): truncate the MS CLEAN-
+    like model and the two p_max = 86 shapelet lobes by cumulative absolute
+    flux (and the lobes by order), predict the peel observation on the mixed
+    path, and report the GPU time beside the error of the truncated model
+    against the oracle's full model on sampled rows (relative to the full
+    model's total flux)."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2005_09316_amd import truncate, vp
+
+    obs, clean, lobes = synth.make_paper_cost_comparison()
+    ctx = vp.vp_create_ctx(0, 0)
+    oh = vp.vp_create_obs(ctx, obs)
+    nrows = obs.n_time * obs.n_bl
+    out = torch.empty((nrows, obs.n_chan), dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = np.sort(np.random.default_rng(7).choice(nrows, check_rows, replace=False))
+    res = {"n_vis": obs.n_vis, "check_rows": check_rows, "models": {}}
+
+    def eff_order(sky):
+        m = 0
+        for s in range(sky.n_shp):
+            N = int(sky.s_nmax[s])
+            c = sky.coeffs[int(sky.s_coeff_off[s]):int(sky.s_coeff_off[s]) + (N + 1) * (N + 2) // 2]
+            n1, n2 = truncate._orders(N)
+            nz = np.flatnonzero(c)
+            m = max(m, int((n1[nz] + n2[nz]).max()) if nz.size else 0)
+        return m
+
+    for name, sky in (("clean", clean), ("shapelet", lobes)):
+        ref = oracle.predict(obs, sky, rows=rows)
+        variants = [("flux", f) + tuple(truncate.truncate_by_flux(sky, f)) for f in fracs]
+        if name == "shapelet":
+            for n in orders:
+                t = truncate.truncate_by_order(sky, n)
+                full_flux = truncate.component_flux(sky)[0]
+                kept_flux = truncate.component_flux(t)[0]
+                variants.append(("order", n, t, int(np.count_nonzero(kept_flux)), full_flux.size,
+                                 float(kept_flux.sum() / full_flux.sum())))
+        rows_out = []
+        for rule, param, t, n, ntot, frac in variants:
+            sh = vp.vp_create_sky(ctx, t)
+            vp.vp_predict(ctx, sh, oh, vp.VP_PREC_MIXED, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize()
+            vp.vp_profile(ctx, True)
+            vp.vp_profile_read(ctx)
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                vp.vp_predict(ctx, sh, oh, vp.VP_PREC_MIXED, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3 / reps
+            c, tk = vp.vp_profile_read(ctx)
+            vp.vp_profile(ctx, False)
+            got = out[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+            err = oracle.error_metric(got, ref, obs, sky)
+            vp.vp_destroy_sky(sh)
+            r = {"rule": rule, "param": param, "kept": int(n), "of": int(ntot),
+                 "kept_frac": round(n / ntot, 4), "flux_frac": round(frac, 5),
+                 "gpu_ms": round(wall, 3),
+                 "kernel_ms": round(float((tk[1] + tk[2]) / max(c[1], 1)), 3),
+                 "err_vs_full_model": err}
+            if name == "shapelet":
+                r["effective_order"] = eff_order(t)
+            rows_out.append(r)
+            _log("truncation %s %s=%s: kept %d/%d (%.0f%%, %.1f%% of |flux|), %.2f ms, error %.2e"
+                 % (name, rule, param, n, ntot, 100.0 * n / ntot, 100.0 * frac, wall, err))
+        res["models"][name] = rows_out
     vp.vp_destroy_obs(oh)
     vp.vp_destroy_ctx(ctx)
     del out
@@ -267,6 +348,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper-cost", action="store_true")
     ap.add_argument("--no-shapelets", action="store_true", help="skip the shapelet-contraction leg")
+    ap.add_argument("--no-truncation", action="store_true", help="skip the truncation sweep")
     ap.add_argument("--only-shapelets", action="store_true",
                     help="run only the shapelet-contraction leg and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,6 +467,7 @@ def main():
 
     paper_cost = None if args.no_paper_cost else paper_cost_comparison()
     shp = None if args.no_shapelets else shapelet_contraction()
+    trunc = None if args.no_truncation else truncation_sweep()
 
     serving = None
     if not args.no_serve:
@@ -408,6 +491,7 @@ def main():
         "serving": serving,
         "paper_cost_comparison": paper_cost,
         "shapelet_contraction": shp,
+        "truncation_sweep": trunc,
     }
     print(json.dumps(line), flush=True)
 

@@ -136,7 +136,11 @@ int vp_destroy_obs(vp_obs *obs); /* VP_EBUSY while a pending job uses it */
 /* Copy a sky model to the device.  Host arrays are read during the call and
  * may be freed on return.  Per-(sky, observation) tables (direction cosines,
  * frames, flux per channel, coefficient tiles) are built on the device by the
- * first predict/subtract that pairs them, and cached.  Errors: VP_EINVAL for
+ * first predict/subtract that pairs them, and cached.  A shapelet is kept to
+ * its effective order, the highest n1 + n2 with a non-zero coefficient
+ * (zero coefficients above it contribute nothing; the shapelet kernels' work
+ * follows the order, so truncating high orders saves time while truncating
+ * scattered coefficients does not).  Errors: VP_EINVAL for
  * negative counts, NULL arrays with a positive count, non-finite values,
  * nu_ref <= 0, Gaussian FWHM < 0, beta <= 0, nmax outside 0..VP_NMAX_LIMIT,
  * coefficient offsets < 0; VP_ENOMEM; VP_EDEVICE. */

@@ -456,11 +456,18 @@ int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *d, vp_sky **out) {
     if (!(d->s_beta1[s] > 0) || !(d->s_beta2[s] > 0)) return set_error(VP_EINVAL, "shapelet %d: beta must be positive", s);
     if (d->s_coeff_off[s] < 0) return set_error(VP_EINVAL, "shapelet %d: negative coefficient offset", s);
     const int64_t cnt = (int64_t)(N + 1) * (N + 2) / 2;
-    if (!finite_all(d->coeffs + d->s_coeff_off[s], cnt)) return set_error(VP_EINVAL, "shapelet %d: non-finite coefficient", s);
-    nmax[s] = N;
+    const double *c = d->coeffs + d->s_coeff_off[s];
+    if (!finite_all(c, cnt)) return set_error(VP_EINVAL, "shapelet %d: non-finite coefficient", s);
+    // effective order: the highest n1 + n2 with a non-zero coefficient (orders
+    // above it contribute nothing, and the kernels' work follows the order)
+    int neff = 0;
+    for (int n1 = 0, i = 0; n1 <= N; ++n1)
+      for (int n2 = 0; n2 <= N - n1; ++n2, ++i)
+        if (c[i] != 0.0) neff = std::max(neff, n1 + n2);
+    nmax[s] = neff;
     coff[s] = ncoef;
-    ncoef += cnt;
-    max_nmax = std::max(max_nmax, N);
+    ncoef += (int64_t)(neff + 1) * (neff + 2) / 2;
+    max_nmax = std::max(max_nmax, neff);
   }
   DeviceGuard g(ctx->device);
   if (!g.ok) return set_error(VP_EDEVICE, "cannot select device");
@@ -476,7 +483,13 @@ int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *d, vp_sky **out) {
   for (int i = 0; i < G; ++i) { ra[P + i] = d->g_ra[i]; dec[P + i] = d->g_dec[i]; sref[P + i] = d->g_sref[i]; alpha[P + i] = d->g_alpha[i]; }
   for (int i = 0; i < S; ++i) {
     ra[P + G + i] = d->s_ra[i]; dec[P + G + i] = d->s_dec[i]; sref[P + G + i] = d->s_sref[i]; alpha[P + G + i] = d->s_alpha[i];
-    std::memcpy(coeffs.data() + coff[i], d->coeffs + d->s_coeff_off[i], sizeof(double) * (size_t)((nmax[i] + 1) * (nmax[i] + 2) / 2));
+    // packed n1-major over n1 + n2 <= nmax, re-packed for the effective order
+    const int N = d->s_nmax[i], M = nmax[i];
+    const double *c = d->coeffs + d->s_coeff_off[i];
+    double *o = coeffs.data() + coff[i];
+    for (int n1 = 0; n1 <= M; ++n1)
+      for (int n2 = 0; n2 <= M - n1; ++n2)
+        *o++ = c[(int64_t)n1 * (N + 1) - (int64_t)n1 * (n1 - 1) / 2 + n2];
   }
   std::vector<int64_t> a32_off(S), c64_off(S), abf_off(S);
   std::vector<int32_t> ld(S);

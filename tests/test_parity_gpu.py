@@ -182,3 +182,32 @@ def test_invalid_inputs_rejected(ctx):
             vp.vp_predict(ctx, h.sky, h.obs, 7, vp.VP_C64, 1234, 0)
         with pytest.raises(vp.VPError):
             vp.vp_predict(ctx, h.sky, h.obs, vp.VP_PREC_MIXED, 5, 1234, 0)
+
+
+def test_effective_order_and_truncation(ctx):
+    """A shapelet whose coefficients vanish above order 20 gives the same
+    visibilities, bit for bit, whether declared with nmax 40 or 20 (the
+    library keeps the effective order); an order-truncated and a flux-truncated
+    model match the oracle of the same truncated model."""
+    import dataclasses
+
+    from paper_2005_09316_amd import truncate
+    obs, sky = synth.make_config(0, n_tiles=16, n_time=2, n_chan=5, n_point=2, n_gauss=1, shapelet_nmax=[40])
+    t40 = truncate.truncate_by_order(sky, 20)
+    n1, n2 = truncate._orders(40)
+    t20 = dataclasses.replace(t40, s_nmax=np.array([20], np.int32), coeffs=t40.coeffs[n1 + n2 <= 20])
+    outs = []
+    for sk in (t40, t20):
+        with Handles(ctx, obs, sk) as h:
+            outs.append(run(ctx, h.obs, h.sky, obs, vp.VP_PREC_MIXED, vp.VP_C128))
+    assert np.array_equal(outs[0], outs[1])
+    ref = oracle.predict(obs, t20)
+    err = oracle.error_metric(outs[1], ref, obs, t20)
+    _log("order-truncated shapelet (20 of 40): error / total flux = %.3e" % err)
+    assert err <= 1e-6
+    tf, n, ntot, frac = truncate.truncate_by_flux(sky, 0.8)
+    with Handles(ctx, obs, tf) as h:
+        got = run(ctx, h.obs, h.sky, obs, vp.VP_PREC_MIXED, vp.VP_C128)
+    err = oracle.error_metric(got, oracle.predict(obs, tf), obs, tf)
+    _log("flux-truncated model (%d of %d kept): error / total flux = %.3e" % (n, ntot, err))
+    assert err <= 1e-6
