@@ -18,6 +18,12 @@ Functions and the paper passages they follow:
   tests can pin each against closed forms.
 * :func:`error_metric` -- max over channels of max |V - V_ref| / F_k with
   F_k = sum_j |S_j(nu_k)| |xi_j(0)|, the total flux per channel.
+* :func:`calibrate_cell`, :func:`peel` -- the calibration and subtraction of
+  Sec. 5.1: model M_ij = g_i g_j^* I_ij, residual R = V - M, the linearised
+  least-squares step for the real and imaginary parts of the gain errors
+  (Eq. peeling-iter) with an explicit design matrix, iterated from unit
+  gains; the step is the minimum-norm least-squares solution (the global
+  phase of the gains is not determined by the data).  Plain numpy.
 
 Every function here is pinned by a test in ``tests/test_oracle_pins.py``.
 """
@@ -253,3 +259,60 @@ def error_metric(v, v_ref, obs, sky) -> float:
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def calibrate_cell(v, model, ant1, ant2, n_ant: int, n_iter: int = 10, g0=None) -> np.ndarray:
+    """Per-tile complex gains for one (time, frequency) cell (Sec. 5.1).
+
+    v, model: [n_bl] complex visibilities of the data and of the ideal model
+    I_ij; ant1, ant2: the tiles of each baseline.  Each iteration linearises
+    V_ij = (g_i + e_i)(g_j + e_j)^* I_ij around the current g: the residual
+    R_ij = V_ij - g_i g_j^* I_ij is matched by e_i g_j^* I_ij + e_j^* g_i I_ij,
+    whose real and imaginary parts are linear in Re e and Im e (the rows of
+    the design matrix A below), and x = (A^T A)^+ A^T b is taken as the
+    minimum-norm least-squares solution.  Then g <- g + e."""
+    v = np.asarray(v, np.complex128)
+    m = np.asarray(model, np.complex128)
+    a1 = np.asarray(ant1, np.int64)
+    a2 = np.asarray(ant2, np.int64)
+    nb = v.size
+    g = np.ones(n_ant, np.complex128) if g0 is None else np.array(g0, np.complex128)
+    rows = np.arange(nb)
+    for _ in range(n_iter):
+        w = np.conj(g[a2]) * m   # coefficient of e_i
+        z = g[a1] * m            # coefficient of e_j^*
+        r = v - g[a1] * np.conj(g[a2]) * m
+        A = np.zeros((2 * nb, 2 * n_ant))
+        # Re R = Re(e_i w) + Re(e_j^* z);  Im R = Im(e_i w) + Im(e_j^* z)
+        np.add.at(A, (rows, a1), w.real)
+        np.add.at(A, (rows, n_ant + a1), -w.imag)
+        np.add.at(A, (rows, a2), z.real)
+        np.add.at(A, (rows, n_ant + a2), z.imag)
+        np.add.at(A, (nb + rows, a1), w.imag)
+        np.add.at(A, (nb + rows, n_ant + a1), w.real)
+        np.add.at(A, (nb + rows, a2), z.imag)
+        np.add.at(A, (nb + rows, n_ant + a2), -z.real)
+        b = np.concatenate([r.real, r.imag])
+        x = np.linalg.lstsq(A, b, rcond=None)[0]
+        g = g + x[:n_ant] + 1j * x[n_ant:]
+    return g
+
+
+def peel(data, model, ant1, ant2, n_ant: int, n_iter: int = 10):
+    """Calibrate every (time, channel) cell of data [T, B, K] against model
+    [T, B, K] and subtract the gain-corrupted model.  Returns (gains [T, K,
+    n_ant], residual [T, B, K])."""
+    data = np.asarray(data, np.complex128)
+    model = np.asarray(model, np.complex128)
+    T, B, K = data.shape
+    gains = np.empty((T, K, n_ant), np.complex128)
+    res = np.empty_like(data)
+    a1 = np.asarray(ant1, np.int64)
+    a2 = np.asarray(ant2, np.int64)
+    for t in range(T):
+        for k in range(K):
+            g = calibrate_cell(data[t, :, k], model[t, :, k], a1, a2, n_ant, n_iter)
+            gains[t, k] = g
+            res[t, :, k] = data[t, :, k] - g[a1] * np.conj(g[a2]) * model[t, :, k]
+    return gains, res
+

@@ -218,6 +218,29 @@ def make_obs(rng: np.random.Generator, n_tiles: int, n_time: int, freq_hz: np.nd
                beam_nu_ref_hz=beam_nu_ref_hz, n_tiles=n_tiles)
 
 
+def antenna_pairs(n_tiles: int):
+    """Tiles (ant1, ant2) of each baseline, in the order of baselines_enu."""
+    i, j = np.triu_indices(n_tiles, k=1)
+    return i.astype(np.int32), j.astype(np.int32)
+
+
+def random_gains(rng: np.random.Generator, n_time: int, n_chan: int, n_ant: int, amp_sigma: float = 0.1,
+                 phase_sigma: float = 0.5) -> np.ndarray:
+    """Synthetic complex tile gains [n_time, n_chan, n_ant]: per tile a random
+    amplitude and phase, a linear slope of each across the band and a small
+    drift in time."""
+    amp0 = 1.0 + amp_sigma * rng.standard_normal(n_ant)
+    ph0 = phase_sigma * rng.standard_normal(n_ant)
+    amp_slope = 0.2 * amp_sigma * rng.standard_normal(n_ant)
+    ph_slope = 0.5 * phase_sigma * rng.standard_normal(n_ant)
+    drift = 0.05 * phase_sigma * rng.standard_normal(n_ant)
+    x = np.linspace(-0.5, 0.5, n_chan) if n_chan > 1 else np.zeros(1)
+    t = np.linspace(-0.5, 0.5, n_time) if n_time > 1 else np.zeros(1)
+    amp = amp0[None, None, :] + amp_slope[None, None, :] * x[None, :, None]
+    ph = ph0[None, None, :] + ph_slope[None, None, :] * x[None, :, None] + drift[None, None, :] * t[:, None, None]
+    return amp * np.exp(1j * ph)
+
+
 def channels(centre_hz: float, width_hz: float, n: int) -> np.ndarray:
     """Centres of n equal bins of width width_hz, centred on centre_hz."""
     return centre_hz + (np.arange(n, dtype=np.float64) - 0.5 * (n - 1)) * width_hz
