@@ -22,11 +22,19 @@ The JSON line carries:
                   `--only-shapelets` runs this leg alone (for profiling);
   truncation_sweep -- the paper's model truncation (Sec. 5.3) on its peel
                   observation: GPU time and error against the full model per
-                  fraction of components kept.
+                  fraction of components kept;
+  calibrated_peel -- the large peel observation (256 tiles, 1 time, 384
+                  channels, complex64 data holding the 10 N=80 shapelet
+                  sources, each under its own synthetic tile gains, plus
+                  noise): the sources peeled one after another with
+                  calibration (Sec. 5.1) on the mixed path; time per source
+                  split into prediction and gain solve, and the residual RMS
+                  against plain (uncalibrated) subtraction.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -207,6 +215,109 @@ def truncation_sweep(check_rows=8, fracs=(1.0, 0.95, 0.9, 0.8, 0.7, 0.5), orders
     return res
 
 
+def calibrated_peel(n_iter=8, check_chan=(17,)):
+    """Workload 4's observation: data = sum over the 10 shapelet sources of
+    g_i g_j^* V_s (a gain table of its own per source) + N(0, 1 Jy) noise,
+    complex64, resident.  Timed: the 10 vp_peel calls in sequence (predict
+    into the workspace, solve gains per (time, channel), subtract).  Beside
+    it: the same data after plain vp_subtract of the 10 sources, and a check
+    of the last source's gains on one channel against the oracle."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2005_09316_amd import vp
+
+    obs, sky = synth.make_config(4)
+    n_ant = int(obs.n_tiles)
+    a1, a2 = synth.antenna_pairs(n_ant)
+    srcs = [synth.select_components(sky, points=[], gauss=[], shapelets=[k]) for k in range(sky.n_shp)]
+    ctx = vp.vp_create_ctx(0, 0)
+    oh = vp.vp_create_obs(ctx, obs)
+    handles = [vp.vp_create_sky(ctx, s) for s in srcs]
+    stream = torch.cuda.current_stream()
+    shape = (obs.n_time, obs.n_bl, obs.n_chan)
+    rng = np.random.default_rng(4040)
+    gains_true = [synth.random_gains(rng, obs.n_time, obs.n_chan, n_ant) for _ in srcs]
+    # build the data on the device: sum_s g_ant1 g_ant2^* V_s + noise
+    data0 = torch.from_numpy(synth.noise_c64(shape, seed=4041)).to("cuda")
+    tmp = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    i1 = torch.as_tensor(a1, dtype=torch.long, device="cuda")
+    i2 = torch.as_tensor(a2, dtype=torch.long, device="cuda")
+    for h, G in zip(handles, gains_true):
+        vp.vp_predict(ctx, h, oh, vp.VP_PREC_MIXED, vp.VP_C64, tmp.data_ptr(), stream.cuda_stream)
+        g = torch.from_numpy(G).to(torch.complex64).to("cuda")          # [T, K, n_ant]
+        corr = (g[:, :, i1] * torch.conj(g[:, :, i2])).permute(0, 2, 1)  # [T, B, K]
+        data0 += corr * tmp
+    torch.cuda.synchronize()
+    rms0 = float(torch.sqrt(torch.mean(torch.abs(data0) ** 2)))
+    # plain subtraction for comparison
+    d = data0.clone()
+    for h in handles:
+        vp.vp_subtract(ctx, h, oh, vp.VP_PREC_MIXED, vp.VP_C64, d.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    rms_plain = float(torch.sqrt(torch.mean(torch.abs(d) ** 2)))
+    gains = torch.empty((len(handles), obs.n_time, obs.n_chan, n_ant), dtype=torch.complex128, device="cuda")
+
+    def run():
+        for s, h in enumerate(handles):
+            vp.vp_peel(ctx, h, oh, a1, a2, n_ant, n_iter, vp.VP_PREC_MIXED, vp.VP_C64, d.data_ptr(),
+                       gains[s].data_ptr(), stream.cuda_stream)
+
+    d.copy_(data0)
+    run()  # warm: tables and workspace
+    torch.cuda.synchronize()
+    d.copy_(data0)
+    torch.cuda.synchronize()
+    vp.vp_profile(ctx, True)
+    vp.vp_profile_read(ctx)
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    c, tk = vp.vp_profile_read(ctx)
+    vp.vp_profile(ctx, False)
+    rms_peel = float(torch.sqrt(torch.mean(torch.abs(d) ** 2)))
+    rms_noise = math.sqrt(2.0)
+    # check: the first source peeled from the original data, on sampled
+    # channels, against the oracle's solution from the same data
+    ks = np.asarray(check_chan)
+    sub = dataclasses.replace(obs, n_chan=int(ks.size), freq_hz=obs.freq_hz[ks])
+    d1 = data0.clone()
+    g1 = torch.empty((obs.n_time, obs.n_chan, n_ant), dtype=torch.complex128, device="cuda")
+    vp.vp_peel(ctx, handles[0], oh, a1, a2, n_ant, n_iter, vp.VP_PREC_MIXED, vp.VP_C64, d1.data_ptr(),
+               g1.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    M = oracle.predict(sub, srcs[0]).reshape(obs.n_time, obs.n_bl, ks.size)
+    din = data0[:, :, torch.as_tensor(ks, device="cuda")].cpu().numpy().astype(np.complex128)
+    g_ref, r_ref = oracle.peel(din, M, a1, a2, n_ant, n_iter)
+    gg = g1[:, torch.as_tensor(ks, device="cuda"), :].cpu().numpy()
+    p = gg[:, :, a1] * np.conj(gg[:, :, a2])
+    p_ref = g_ref[:, :, a1] * np.conj(g_ref[:, :, a2])
+    r_got = d1[:, :, torch.as_tensor(ks, device="cuda")].cpu().numpy().astype(np.complex128)
+    check = {"source": 0, "channels": ks.tolist(),
+             "gain_products_rel_err": float(np.abs(p - p_ref).max() / np.abs(p_ref).max()),
+             "residual_err_vs_total_flux": oracle.error_metric(r_got, r_ref, sub, srcs[0])}
+    res = {"n_vis": obs.n_vis, "n_sources": len(handles), "n_ant": n_ant, "n_iter": n_iter,
+           "cells": obs.n_time * obs.n_chan, "ms_total": round(wall, 3),
+           "ms_per_source": round(wall / len(handles), 3),
+           "predict_kernel_ms": round(float(tk[1] + tk[2]), 3),
+           "gain_solve_kernel_ms": round(float(tk[3]), 3), "gain_solve_launches": int(c[3]),
+           "rms_data_jy": rms0, "rms_after_plain_subtract_jy": rms_plain,
+           "rms_after_calibrated_peel_jy": rms_peel, "rms_noise_jy": rms_noise,
+           "oracle_check": check}
+    _log("calibrated peel: %d sources x %.2f ms (predict %.2f ms, gain solve %.2f ms in total); rms %.3f -> plain "
+         "%.3f, peeled %.3f (noise %.3f) Jy; check %s" % (len(handles), wall / len(handles), tk[1] + tk[2], tk[3],
+                                                         rms0, rms_plain, rms_peel, rms_noise, check))
+    for h in handles:
+        vp.vp_destroy_sky(h)
+    vp.vp_destroy_obs(oh)
+    vp.vp_destroy_ctx(ctx)
+    del d, d1, data0, tmp, gains, g1
+    torch.cuda.empty_cache()
+    return res
+
+
 def _pg_source_hash():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2005_09316_amd", "csrc", "vp_kernels.hip")).read()
@@ -349,14 +460,16 @@ def main():
     ap.add_argument("--no-paper-cost", action="store_true")
     ap.add_argument("--no-shapelets", action="store_true", help="skip the shapelet-contraction leg")
     ap.add_argument("--no-truncation", action="store_true", help="skip the truncation sweep")
+    ap.add_argument("--no-peel", action="store_true", help="skip the calibrated-peel leg")
+    ap.add_argument("--only-peel", action="store_true", help="run the calibrated-peel leg alone")
     ap.add_argument("--only-shapelets", action="store_true",
                     help="run only the shapelet-contraction leg and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (its HBM counters scale the kernels')")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how "
-              "the work would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -366,6 +479,9 @@ def main():
 
     if args.only_shapelets:
         print(json.dumps(shapelet_contraction()), flush=True)
+        return
+    if args.only_peel:
+        print(json.dumps(calibrated_peel()), flush=True)
         return
 
     t_gen = time.time()
@@ -468,6 +584,7 @@ def main():
     paper_cost = None if args.no_paper_cost else paper_cost_comparison()
     shp = None if args.no_shapelets else shapelet_contraction()
     trunc = None if args.no_truncation else truncation_sweep()
+    peel = None if args.no_peel else calibrated_peel()
 
     serving = None
     if not args.no_serve:
@@ -492,6 +609,7 @@ def main():
         "paper_cost_comparison": paper_cost,
         "shapelet_contraction": shp,
         "truncation_sweep": trunc,
+        "calibrated_peel": peel,
     }
     print(json.dumps(line), flush=True)
 

@@ -82,6 +82,9 @@ extern "C" {
 
 /* maximum shapelet order n1 + n2 */
 #define VP_NMAX_LIMIT 96
+#define VP_PEEL_MAX_ANT 256   /* tiles a peel can calibrate (one thread per tile) */
+#define VP_PEEL_MAX_ITER 1000 /* Gauss-Newton iterations accepted by vp_peel */
+#define VP_PEEL_MAX_CG 200    /* conjugate-gradient steps per Gauss-Newton step (bound) */
 
 typedef struct vp_ctx vp_ctx;
 typedef struct vp_obs vp_obs;
@@ -194,12 +197,35 @@ int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res);
 /* HBM footprint (bytes) that admission charges for `job`.  Errors: VP_EINVAL. */
 int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes);
 
+/* Peel with calibration (Sec. 5.1): predict the model I of `sky` (the source
+ * to peel) on `obs` into a library workspace, fit per-tile complex gains g
+ * for every (time, channel) cell so that g_ant1 g_ant2^* I matches the data
+ * -- n_iter Gauss-Newton iterations of the linearised least-squares problem
+ * of Sec. 5.1, starting from unit gains, each step the minimum-norm
+ * least-squares solution (the data leave one global phase free per
+ * connected group of tiles; a step stops early once the right-hand side is
+ * at FP64 rounding level) -- and subtract: data <- data - g_ant1 g_ant2^* I.
+ * ant1, ant2: host arrays [n_bl] (n_bl of obs), the tiles (0..n_ant-1,
+ * distinct, each pair at most once) of each baseline, the same for every
+ * time step; read during the call only.
+ * gains_dev: caller-owned device memory [n_time][n_chan][n_ant] complex128
+ * receiving the gains, or NULL.  data_dev as for vp_subtract.  Asynchronous
+ * on hip_stream; calls on one context share a workspace of n_time x n_bl x
+ * n_chan complex values and wait for the previous call to finish with it.
+ * Errors: VP_EINVAL (tiles out of range or repeated pairs, n_ant outside
+ * 2..VP_PEEL_MAX_ANT, n_iter outside 0..VP_PEEL_MAX_ITER, as vp_subtract),
+ * VP_ENOMEM, VP_EDEVICE. */
+int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *ant1, const int32_t *ant2,
+            int32_t n_ant, int32_t n_iter, int precision, int dtype, void *data_dev, void *gains_dev,
+            void *hip_stream);
+
 /* Per-kernel timing, for measurement.  When enabled, the library records HIP
  * events around each kernel it launches for vp_predict/vp_subtract on the
  * caller's stream and accumulates their durations by kernel class:
  * 0 = per-(sky,obs) table build, 1 = point/Gaussian tile kernel,
- * 2 = shapelet tile kernel.  vp_profile_read synchronises the recorded events,
- * fills counts[3] and total_ms[3], and resets the accumulators. */
+ * 2 = shapelet tile kernel, 3 = peel calibration.  vp_profile_read
+ * synchronises the recorded events, fills counts[4] and total_ms[4], and
+ * resets the accumulators. */
 int vp_profile(vp_ctx *ctx, int enable);
 int vp_profile_read(vp_ctx *ctx, int64_t *counts, double *total_ms);
 

@@ -355,6 +355,14 @@ int vp_destroy_ctx(vp_ctx *ctx) {
       (void)hipEventDestroy(r.e1);
     }
   }
+  if (ctx->peel) {
+    if (ctx->peel->done) {
+      (void)hipEventSynchronize(ctx->peel->done);
+      (void)hipEventDestroy(ctx->peel->done);
+    }
+    ctx->peel->mem.release();
+    delete ctx->peel;
+  }
   delete ctx;
   return VP_OK;
 }
@@ -599,15 +607,15 @@ int vp_profile_read(vp_ctx *ctx, int64_t *counts, double *total_ms) {
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     recs.swap(ctx->prof_pending);
   }
-  int64_t c[3] = {0, 0, 0};
-  double t[3] = {0, 0, 0};
+  int64_t c[kProfClasses] = {0, 0, 0, 0};
+  double t[kProfClasses] = {0, 0, 0, 0};
   int rc = VP_OK;
   for (auto &r : recs) {
     float ms = 0.f;
     hipError_t e = hipEventSynchronize(r.e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.e0, r.e1);
     if (e != hipSuccess && rc == VP_OK) rc = hip_error(e, "reading kernel timings");
-    if (e == hipSuccess && r.kind >= 0 && r.kind < 3) {
+    if (e == hipSuccess && r.kind >= 0 && r.kind < kProfClasses) {
       c[r.kind] += 1;
       t[r.kind] += ms;
     }
@@ -615,7 +623,7 @@ int vp_profile_read(vp_ctx *ctx, int64_t *counts, double *total_ms) {
     (void)hipEventDestroy(r.e1);
   }
   if (rc != VP_OK) return rc;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < kProfClasses; ++i) {
     counts[i] = c[i];
     total_ms[i] = t[i];
   }

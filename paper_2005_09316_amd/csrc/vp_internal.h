@@ -145,6 +145,27 @@ struct ServeDev {        // device memory
   uint64_t tdone[kServeSlots];
 };
 
+// Kernel classes timed by vp_profile: tables, point/Gaussian, shapelet, calibration.
+constexpr int kProfClasses = 4;
+
+// Peel calibration (vp_calib.hip).
+constexpr int kPeelMaxAnt = 256;          // tiles per observation (one thread each)
+constexpr size_t kPeelSmemMax = 163840;  // LDS per workgroup on gfx950
+
+struct GainArgs {
+  int T, B, K;            // cells are (time, channel); B baselines per time step
+  int n_ant, n_iter, max_cg;
+  double cg_tol2;         // squared relative residual that ends a CG solve
+  const void *model;      // [T][B][K] complex ideal model I (same type as data)
+  void *data;             // [T][B][K] complex data V; the residual on return when subtract
+  int c64;                // 1: complex64, 0: complex128
+  const int32_t *ant1, *ant2;  // [B] tiles of each baseline
+  const int32_t *pair_bl;      // [n_ant (n_ant - 1) / 2] baseline of tile pair (i < j), -1 if none
+  const int32_t *comp;         // [n_ant] connected component of each tile in the baseline graph, -1 if idle
+  double2 *gains;         // [T][K][n_ant] output, or null
+  int subtract;
+};
+
 // Host-side launchers (vp_kernels.hip).
 hipError_t launch_derive(const DeriveArgs &a, hipStream_t s);
 hipError_t launch_flux(const FluxArgs &a, hipStream_t s);
@@ -154,6 +175,8 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s);
 hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
                         hipStream_t s);
 hipError_t serve_grid(int *grid);
+hipError_t launch_gain(const GainArgs &a, hipStream_t s);
+size_t gain_smem_bytes(int n_ant, bool w64);
 
 // sizes of per-shapelet tile storage
 inline int64_t a32_floats(int nmax) { return (int64_t)shp_pairs(nmax) * kA32PerPair; }

@@ -25,6 +25,19 @@ struct DeviceMem {
   void release();
 };
 
+// Device workspace of vp_peel: the model visibilities and the baseline
+// tables.  Calls on one context take turns on it (mu, and the event of the
+// previous call's last kernel).
+struct PeelWork {
+  std::mutex mu;
+  DeviceMem mem;
+  void *model = nullptr;
+  size_t model_bytes = 0;
+  int32_t *tab = nullptr;  // ant1 [B], ant2 [B], pair_bl [n_pairs]
+  size_t tab_n = 0;
+  hipEvent_t done = nullptr;
+};
+
 struct DerivedEntry {
   Derived d{};
   DeviceMem mem;
@@ -130,4 +143,5 @@ struct vp_ctx {
   std::mutex prof_mu;
   std::vector<vp::ProfRecord> prof_pending;
   vp::Scheduler *sched = nullptr;
+  vp::PeelWork *peel = nullptr;
 };

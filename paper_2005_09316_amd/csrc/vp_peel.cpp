@@ -1,0 +1,123 @@
+// vp_peel.cpp -- vp_peel: predict a source's model, calibrate it against the
+// data per (time, channel) and subtract the gain-corrupted model (Sec. 5.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/vp.h"
+#include "vp_internal.h"
+#include "vp_objects.h"
+
+using namespace vp;
+
+extern "C" {
+
+int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *ant1, const int32_t *ant2,
+            int32_t n_ant, int32_t n_iter, int precision, int dtype, void *data_dev, void *gains_dev,
+            void *hip_stream) {
+  int rc = check_call(ctx, sky, obs, precision, dtype, data_dev);
+  if (rc != VP_OK) return rc;
+  if (!ant1 || !ant2) return set_error(VP_EINVAL, "NULL tile arrays");
+  if (n_ant < 2 || n_ant > VP_PEEL_MAX_ANT)
+    return set_error(VP_EINVAL, "n_ant %d outside 2..%d", n_ant, VP_PEEL_MAX_ANT);
+  if (n_iter < 0 || n_iter > VP_PEEL_MAX_ITER)
+    return set_error(VP_EINVAL, "n_iter %d outside 0..%d", n_iter, VP_PEEL_MAX_ITER);
+  const int B = obs->B;
+  const int npairs = n_ant * (n_ant - 1) / 2;
+  // tables: ant1 [B], ant2 [B], baseline of each tile pair [npairs], and
+  // the connected component of each tile [n_ant] (-1: no baseline)
+  std::vector<int32_t> tab((size_t)2 * B + npairs + n_ant, -1);
+  for (int b = 0; b < B; ++b) {
+    const int i = ant1[b], j = ant2[b];
+    if (i < 0 || j < 0 || i >= n_ant || j >= n_ant || i == j)
+      return set_error(VP_EINVAL, "baseline %d joins tiles %d and %d", b, i, j);
+    const int lo = std::min(i, j), hi = std::max(i, j);
+    int32_t &slot = tab[(size_t)2 * B + (size_t)lo * n_ant - (size_t)lo * (lo + 1) / 2 + (hi - lo - 1)];
+    if (slot >= 0) return set_error(VP_EINVAL, "baselines %d and %d join the same tiles", slot, b);
+    slot = b;
+    tab[b] = i;
+    tab[(size_t)B + b] = j;
+  }
+  {
+    // union-find over the baselines; a component is named by its root tile
+    std::vector<int32_t> up(n_ant);
+    for (int k = 0; k < n_ant; ++k) up[k] = k;
+    auto root = [&](int k) {
+      while (up[k] != k) k = up[k] = up[up[k]];
+      return k;
+    };
+    std::vector<char> used(n_ant, 0);
+    for (int b = 0; b < B; ++b) {
+      const int ri = root(ant1[b]), rj = root(ant2[b]);
+      used[ant1[b]] = used[ant2[b]] = 1;
+      if (ri != rj) up[std::max(ri, rj)] = std::min(ri, rj);
+    }
+    int32_t *comp = tab.data() + 2 * (size_t)B + npairs;
+    for (int k = 0; k < n_ant; ++k) comp[k] = used[k] ? root(k) : -1;
+  }
+  if (gain_smem_bytes(n_ant, false) > kPeelSmemMax) return set_error(VP_EINVAL, "too many tiles");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return set_error(VP_EDEVICE, "cannot select device");
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->peel) ctx->peel = new PeelWork();
+  }
+  PeelWork &w = *ctx->peel;
+  std::lock_guard<std::mutex> lk(w.mu);
+  hipError_t e = hipSuccess;
+  // the previous call's kernels have finished with the workspace
+  if (w.done) e = hipEventSynchronize(w.done);
+  if (e != hipSuccess) return hip_error(e, "waiting for the previous peel");
+  const size_t mbytes = (size_t)obs->T * B * obs->K * (dtype == VP_C64 ? 8 : 16);
+  if (mbytes > w.model_bytes || tab.size() > w.tab_n) {
+    w.mem.release();
+    w.model = nullptr;
+    w.tab = nullptr;
+    w.model_bytes = std::max(mbytes, w.model_bytes);
+    w.tab_n = std::max(tab.size(), w.tab_n);
+    e = w.mem.alloc(&w.model, w.model_bytes);
+    if (e == hipSuccess) e = w.mem.alloc((void **)&w.tab, sizeof(int32_t) * w.tab_n);
+    if (e != hipSuccess) {
+      w.mem.release();
+      w.model = nullptr;
+      w.tab = nullptr;
+      w.model_bytes = w.tab_n = 0;
+      return hip_error(e, "allocating the peel workspace");
+    }
+  }
+  e = hipMemcpy(w.tab, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_error(e, "uploading the baseline tables");
+  hipStream_t s = (hipStream_t)hip_stream;
+  rc = run_tiles(ctx, sky, obs, precision, dtype, w.model, 0, s);
+  if (rc != VP_OK) return rc;
+  GainArgs a;
+  a.T = obs->T;
+  a.B = B;
+  a.K = obs->K;
+  a.n_ant = n_ant;
+  a.n_iter = n_iter;
+  a.max_cg = VP_PEEL_MAX_CG;
+  a.cg_tol2 = 1e-24;
+  a.model = w.model;
+  a.data = data_dev;
+  a.c64 = dtype == VP_C64;
+  a.ant1 = w.tab;
+  a.ant2 = w.tab + B;
+  a.pair_bl = w.tab + 2 * (size_t)B;
+  a.comp = a.pair_bl + npairs;
+  a.gains = (double2 *)gains_dev;
+  a.subtract = 1;
+  {
+    ProfScope ps(ctx, s, 3);
+    e = launch_gain(a, s);
+  }
+  if (e != hipSuccess) return hip_error(e, "launching the gain solve");
+  if (!w.done) e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(w.done, s);
+  if (e != hipSuccess) return hip_error(e, "recording the peel event");
+  return VP_OK;
+}
+
+}  // extern "C"

@@ -27,6 +27,7 @@ VP_PREC_MIXED_F32MMA = 5
 VP_C128, VP_C64 = 0, 1
 VP_JOB_PREDICT, VP_JOB_SUBTRACT = 0, 1
 VP_NMAX_LIMIT = 96
+VP_PEEL_MAX_ANT, VP_PEEL_MAX_ITER, VP_PEEL_MAX_CG = 256, 1000, 200
 
 PRECISIONS = {"fp64": VP_PREC_FP64, "mixed": VP_PREC_MIXED, "mixed_bf16": VP_PREC_MIXED_BF16,
               "fp32": VP_PREC_FP32, "mixed_bf16x2": VP_PREC_MIXED_BF16X2,
@@ -34,7 +35,7 @@ PRECISIONS = {"fp64": VP_PREC_FP64, "mixed": VP_PREC_MIXED, "mixed_bf16": VP_PRE
 
 # every symbol declared in include/vp.h
 EXPORTS = ["vp_create_ctx", "vp_destroy_ctx", "vp_create_obs", "vp_destroy_obs", "vp_create_sky",
-           "vp_destroy_sky", "vp_predict", "vp_subtract", "vp_submit", "vp_poll", "vp_job_footprint",
+           "vp_destroy_sky", "vp_predict", "vp_subtract", "vp_peel", "vp_submit", "vp_poll", "vp_job_footprint",
            "vp_profile", "vp_profile_read", "vp_last_error", "vp_version"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
         "vp_destroy_sky": ([vp], ctypes.c_int),
         "vp_predict": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
         "vp_subtract": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
+        "vp_peel": ([vp, vp, vp, _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int, vp, vp,
+                     vp], ctypes.c_int),
         "vp_submit": ([vp, ctypes.POINTER(vp_job), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "vp_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(vp_job_result)], ctypes.c_int),
         "vp_job_footprint": ([vp, ctypes.POINTER(vp_job), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -200,6 +203,17 @@ def vp_subtract(ctx: int, sky: int, obs: int, precision: int, dtype: int, data_d
     _check(load().vp_subtract(ctx, sky, obs, int(precision), int(dtype), data_dev, hip_stream or None))
 
 
+def vp_peel(ctx: int, sky: int, obs: int, ant1, ant2, n_ant: int, n_iter: int, precision: int, dtype: int,
+            data_dev: int, gains_dev: int = 0, hip_stream: int = 0):
+    """Calibrated peel of `sky` from the data (Sec. 5.1); ant1/ant2: int32 [n_bl] tile of each baseline."""
+    a1 = np.ascontiguousarray(ant1, dtype=np.int32)
+    a2 = np.ascontiguousarray(ant2, dtype=np.int32)
+    if a1.shape != a2.shape or a1.ndim != 1:
+        raise ValueError("ant1 and ant2 must be 1-D arrays of one length")
+    _check(load().vp_peel(ctx, sky, obs, _p(a1, _i32p), _p(a2, _i32p), int(n_ant), int(n_iter), int(precision),
+                          int(dtype), data_dev, gains_dev or None, hip_stream or None))
+
+
 def vp_submit(ctx: int, kind: int, sky: int, obs: int, precision: int, dtype: int, vis_dev: int,
               t_arrival_ns: int = 0) -> int:
     j = vp_job(int(kind), sky, obs, int(precision), int(dtype), vis_dev, int(t_arrival_ns))
@@ -231,8 +245,9 @@ def vp_profile(ctx: int, enable: bool):
 
 
 def vp_profile_read(ctx: int):
-    """(counts[3], total_ms[3]) for kernel classes 0 = tables, 1 = point/Gaussian, 2 = shapelet."""
-    c = np.zeros(3, np.int64)
-    t = np.zeros(3, np.float64)
+    """(counts[4], total_ms[4]) for kernel classes 0 = tables, 1 = point/Gaussian, 2 = shapelet,
+    3 = peel calibration."""
+    c = np.zeros(4, np.int64)
+    t = np.zeros(4, np.float64)
     _check(load().vp_profile_read(ctx, _p(c, _i64p), _p(t)))
     return c, t

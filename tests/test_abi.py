@@ -50,3 +50,8 @@ def test_null_arguments_are_rejected_before_any_device_work():
     assert lib.vp_create_sky(None, None, None) == vp.VP_EINVAL
     assert lib.vp_predict(None, None, None, 1, 1, None, None) == vp.VP_EINVAL
     assert "NULL" in vp.vp_last_error()
+
+
+def test_peel_null_arguments_are_rejected_before_any_device_work():
+    lib = vp.load()
+    assert lib.vp_peel(None, None, None, None, None, 4, 1, 0, 0, None, None, None) == vp.VP_EINVAL

@@ -1,0 +1,267 @@
+"""GPU parity of the calibrated peel (Sec. 5.1): vp_peel against oracle.peel
+on the same seeded data -- gains per (time, channel, tile) and the residual
+after subtracting the gain-corrupted model.
+
+Data: the peeled source's model (the oracle's) corrupted by synthetic tile
+gains, plus the rest of the sky uncorrupted, plus complex N(0, 1 Jy) noise.
+
+Bars.  The GPU model differs from the oracle's by at most the predict bar
+(1e-11 of the peeled total flux F_k on the FP64 path, 1e-6 on the mixed
+paths).  Perturbing the oracle's own model by random errors of that size
+moves its solution by 13x that (gains, relative to max |g|) and 3.1x
+(residual, relative to F_k) on the Fornax-like case below; the bars are
+those factors rounded up, with a margin of about 2.5: gains 30x, residual 8x
+the predict bar.  The conjugate-gradient solve of each Gauss-Newton step
+stops at a relative residual of 1e-12, far below both."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2005_09316_amd import vp
+
+pytestmark = pytest.mark.gpu
+
+PRED_BAR = {vp.VP_PREC_FP64: 1e-11, vp.VP_PREC_MIXED: 1e-6}
+GAIN_FACTOR, RES_FACTOR = 30.0, 8.0
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = vp.vp_create_ctx(0, 0)
+    yield c
+    vp.vp_destroy_ctx(c)
+
+
+def _corrupt(M, G, a1, a2):
+    """V_b = g_ant1 g_ant2^* M_b per (t, b, k); G [T, K, n_ant]."""
+    g1 = np.transpose(G[:, :, a1], (0, 2, 1))
+    g2 = np.transpose(G[:, :, a2], (0, 2, 1))
+    return g1 * np.conj(g2) * M
+
+
+def _make(n_tiles=16, n_time=2, n_chan=5, n_ant=None, keep=None, swap=None, seed=5):
+    """(obs, peel_sky, ant1, ant2, n_ant, data [T, B, K], model [T, B, K]) on
+    the Fornax-like sky: two shapelet lobes peeled, the core point source left
+    in the data uncorrupted."""
+    obs, sky = synth.make_config(2, n_tiles=n_tiles, n_time=n_time, n_chan=n_chan, shapelet_nmax=[30, 30])
+    a1, a2 = synth.antenna_pairs(n_tiles)
+    if keep is not None:
+        obs = dataclasses.replace(obs, n_bl=int(len(keep)), uvw_m=np.ascontiguousarray(obs.uvw_m[:, keep]))
+        a1, a2 = a1[keep], a2[keep]
+    if swap is not None:
+        a1, a2 = np.where(swap, a2, a1).astype(np.int32), np.where(swap, a1, a2).astype(np.int32)
+    n_ant = n_tiles if n_ant is None else n_ant
+    peel_sky = synth.select_components(sky, points=[], gauss=[], shapelets=None)
+    rest = synth.select_components(sky, points=None, gauss=None, shapelets=[])
+    shape = (obs.n_time, obs.n_bl, obs.n_chan)
+    M = oracle.predict(obs, peel_sky).reshape(shape)
+    R = oracle.predict(obs, rest).reshape(shape)
+    rng = np.random.default_rng(seed)
+    G = synth.random_gains(rng, obs.n_time, obs.n_chan, n_ant)
+    noise = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    data = _corrupt(M, G, a1, a2) + R + noise
+    return obs, peel_sky, a1, a2, n_ant, data, M
+
+
+def _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, n_iter, prec, dtype):
+    import torch
+    tdt = torch.complex64 if dtype == vp.VP_C64 else torch.complex128
+    d = torch.from_numpy(np.ascontiguousarray(data)).to(tdt).to("cuda")
+    gains = torch.full((obs.n_time, obs.n_chan, n_ant), complex("nan+nanj"), dtype=torch.complex128,
+                       device="cuda")
+    oh = vp.vp_create_obs(ctx, obs)
+    sh = vp.vp_create_sky(ctx, peel_sky)
+    try:
+        s = torch.cuda.current_stream()
+        vp.vp_peel(ctx, sh, oh, a1, a2, n_ant, n_iter, prec, dtype, d.data_ptr(), gains.data_ptr(),
+                   s.cuda_stream)
+        s.synchronize()
+    finally:
+        vp.vp_destroy_sky(sh)
+        vp.vp_destroy_obs(oh)
+    return gains.cpu().numpy(), d.cpu().numpy().astype(np.complex128)
+
+
+def _input_as(data, dtype):
+    """The data as the library sees them (complex64 rounds the input)."""
+    return data.astype(np.complex64).astype(np.complex128) if dtype == vp.VP_C64 else data
+
+
+def _res_err(res, ref, obs, peel_sky):
+    return oracle.error_metric(res, ref, obs, peel_sky)
+
+
+@pytest.mark.parametrize("prec,dtype", [(vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C128),
+                                        (vp.VP_PREC_MIXED, vp.VP_C64)])
+def test_peel_matches_oracle(ctx, prec, dtype):
+    obs, peel_sky, a1, a2, n_ant, data, M = _make()
+    _log("peel fornax-like 16 tiles x2 times x5 ch, prec", prec, "dtype", dtype)
+    data = _input_as(data, dtype)
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 10, prec, dtype)
+    g_ref, res_ref = oracle.peel(data, M, a1, a2, n_ant, 10)
+    eg = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    er = _res_err(res, res_ref, obs, peel_sky)
+    _log("  gains %.3e (bar %.1e), residual / F %.3e (bar %.1e)"
+         % (eg, GAIN_FACTOR * PRED_BAR[prec], er, RES_FACTOR * PRED_BAR[prec]))
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(res))
+    bar = max(PRED_BAR[prec], 1e-6 if dtype == vp.VP_C64 else 0.0)
+    assert eg <= GAIN_FACTOR * bar
+    assert er <= RES_FACTOR * bar
+
+
+def test_peel_ragged_baselines_and_idle_tiles(ctx):
+    """A subset of the tile pairs (flagged baselines), some with the tiles in
+    the other order, and two tiles that no baseline uses: their gains stay 1."""
+    rng = np.random.default_rng(77)
+    nb = 16 * 15 // 2
+    keep = np.sort(rng.choice(nb, 97, replace=False))
+    swap = rng.random(keep.size) < 0.3
+    obs, peel_sky, a1, a2, n_ant, data, M = _make(n_tiles=16, n_time=3, n_chan=3, n_ant=18, keep=keep,
+                                                  swap=swap, seed=6)
+    _log("peel ragged: %d baselines, %d swapped, n_ant %d" % (obs.n_bl, int(swap.sum()), n_ant))
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 8, vp.VP_PREC_FP64, vp.VP_C128)
+    g_ref, res_ref = oracle.peel(data, M, a1, a2, n_ant, 8)
+    eg = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    er = _res_err(res, res_ref, obs, peel_sky)
+    _log("  gains %.3e, residual / F %.3e" % (eg, er))
+    assert np.array_equal(g[:, :, 16:], np.ones_like(g[:, :, 16:]))
+    assert eg <= GAIN_FACTOR * PRED_BAR[vp.VP_PREC_FP64]
+    assert er <= RES_FACTOR * PRED_BAR[vp.VP_PREC_FP64]
+
+
+def test_peel_disconnected_baseline_graph(ctx):
+    """Only baselines within tiles 0-7 and within tiles 8-15: two groups whose
+    relative phase the data do not fix; each keeps the minimum-norm gauge."""
+    a1, a2 = synth.antenna_pairs(16)
+    keep = np.flatnonzero((a1 < 8) == (a2 < 8))
+    obs, peel_sky, a1, a2, n_ant, data, M = _make(n_tiles=16, n_time=1, n_chan=3, keep=keep, seed=9)
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 30, vp.VP_PREC_FP64, vp.VP_C128)
+    g_ref, res_ref = oracle.peel(data, M, a1, a2, n_ant, 30)
+    eg = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    er = _res_err(res, res_ref, obs, peel_sky)
+    _log("peel two tile groups: gains %.3e, residual / F %.3e" % (eg, er))
+    assert eg <= GAIN_FACTOR * PRED_BAR[vp.VP_PREC_FP64]
+    assert er <= RES_FACTOR * PRED_BAR[vp.VP_PREC_FP64]
+
+
+def test_peel_converged_iterations_keep_the_gauge(ctx):
+    """Far more Gauss-Newton iterations than convergence needs: once the
+    right-hand side is rounding noise the steps must stay at rounding level
+    (no drift of the free global phase)."""
+    obs, peel_sky, a1, a2, n_ant, data, M = _make(n_time=1, n_chan=2, seed=10)
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 40, vp.VP_PREC_FP64, vp.VP_C128)
+    g_ref, res_ref = oracle.peel(data, M, a1, a2, n_ant, 40)
+    eg = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    _log("peel 40 iterations: gains %.3e" % eg)
+    assert eg <= GAIN_FACTOR * PRED_BAR[vp.VP_PREC_FP64]
+
+
+def test_peel_zero_iterations_is_plain_subtraction(ctx):
+    import torch
+    obs, peel_sky, a1, a2, n_ant, data, M = _make(n_time=1, n_chan=4)
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 0, vp.VP_PREC_FP64, vp.VP_C128)
+    assert np.array_equal(g, np.ones_like(g))
+    d = torch.from_numpy(np.ascontiguousarray(data)).to("cuda")
+    oh = vp.vp_create_obs(ctx, obs)
+    sh = vp.vp_create_sky(ctx, peel_sky)
+    s = torch.cuda.current_stream()
+    vp.vp_subtract(ctx, sh, oh, vp.VP_PREC_FP64, vp.VP_C128, d.data_ptr(), s.cuda_stream)
+    s.synchronize()
+    vp.vp_destroy_sky(sh)
+    vp.vp_destroy_obs(oh)
+    sub = d.cpu().numpy()
+    err = _res_err(res, sub, obs, peel_sky)
+    _log("peel n_iter=0 vs vp_subtract: %.3e of F" % err)
+    assert err <= 1e-13
+
+
+def test_peel_many_tiles_fp32_weights(ctx):
+    """n_ant = 200 puts the |I|^2 table in LDS as FP32 (the FP64 table no
+    longer fits); the normal matrix changes at the 1e-7 level, the right-hand
+    side does not, so the Gauss-Newton fixed point is the same and only the
+    free global phase of the gains may differ: compare g_i g_j^* and the
+    residual."""
+    obs, peel_sky, a1, a2, n_ant, data, M = _make(n_tiles=16, n_time=1, n_chan=3, n_ant=200, seed=8)
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 10, vp.VP_PREC_FP64, vp.VP_C128)
+    g_ref, res_ref = oracle.peel(data, M, a1, a2, n_ant, 10)
+    p = g[:, :, a1] * np.conj(g[:, :, a2])
+    p_ref = g_ref[:, :, a1] * np.conj(g_ref[:, :, a2])
+    ep = np.abs(p - p_ref).max() / np.abs(p_ref).max()
+    er = _res_err(res, res_ref, obs, peel_sky)
+    _log("peel n_ant 200 (FP32 weights): g_i g_j^* %.3e, residual / F %.3e" % (ep, er))
+    assert np.array_equal(g[:, :, 16:], np.ones_like(g[:, :, 16:]))
+    assert ep <= 1e-8
+    assert er <= 1e-9
+
+
+def test_peel_full_size_sampled_channels(ctx):
+    """Workload 4's observation (256 tiles, 32640 baselines, 1 time, 384
+    channels, complex64 data): peel one N=80 shapelet with calibration on the
+    mixed path; compare two sampled channels with the oracle.  The data of the
+    sampled channels are the oracle's model corrupted by gains plus noise; the
+    other channels hold noise only (every cell is solved independently)."""
+    obs, sky = synth.make_config(4)
+    src = synth.select_components(sky, points=[], gauss=[], shapelets=[0])
+    a1, a2 = synth.antenna_pairs(256)
+    n_ant, n_iter = 256, 5
+    ks = np.array([17, 301])
+    sub = dataclasses.replace(obs, n_chan=int(ks.size), freq_hz=obs.freq_hz[ks])
+    M = oracle.predict(sub, src).reshape(1, obs.n_bl, ks.size)
+    rng = np.random.default_rng(404)
+    G = synth.random_gains(rng, 1, ks.size, n_ant)
+    data = synth.noise_c64((obs.n_bl, obs.n_chan), seed=405).reshape(1, obs.n_bl, obs.n_chan)
+    data = data.astype(np.complex128)
+    data[:, :, ks] += _corrupt(M, G, a1, a2)
+    data = _input_as(data, vp.VP_C64)
+    _log("peel full size: 256 tiles x 384 ch, sampled channels", ks.tolist())
+    g, res = _run_peel(ctx, obs, src, a1, a2, n_ant, data, n_iter, vp.VP_PREC_MIXED, vp.VP_C64)
+    g_ref, res_ref = oracle.peel(data[:, :, ks], M, a1, a2, n_ant, n_iter)
+    gs = g[:, ks, :]
+    p = gs[:, :, a1] * np.conj(gs[:, :, a2])
+    p_ref = g_ref[:, :, a1] * np.conj(g_ref[:, :, a2])
+    ep = np.abs(p - p_ref).max() / np.abs(p_ref).max()
+    er = oracle.error_metric(res[:, :, ks], res_ref, sub, src)
+    _log("  g_i g_j^* %.3e, residual / F %.3e" % (ep, er))
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(res))
+    assert ep <= GAIN_FACTOR * PRED_BAR[vp.VP_PREC_MIXED]
+    assert er <= RES_FACTOR * PRED_BAR[vp.VP_PREC_MIXED]
+
+
+@pytest.mark.parametrize("bad", ["repeat", "range", "self", "n_ant", "n_iter"])
+def test_peel_rejects_bad_arguments(ctx, bad):
+    obs, sky = synth.make_config(0, n_tiles=6, n_chan=2)
+    a1, a2 = synth.antenna_pairs(6)
+    n_ant, n_iter = 6, 3
+    if bad == "repeat":
+        a1, a2 = a1.copy(), a2.copy()
+        a1[1], a2[1] = a2[0], a1[0]  # the first pair again, tiles swapped
+    elif bad == "range":
+        a2 = a2.copy()
+        a2[-1] = 6
+    elif bad == "self":
+        a2 = a2.copy()
+        a2[2] = a1[2]
+    elif bad == "n_ant":
+        n_ant = 257
+    elif bad == "n_iter":
+        n_iter = -1
+    import torch
+    d = torch.zeros((obs.n_time, obs.n_bl, obs.n_chan), dtype=torch.complex128, device="cuda")
+    oh = vp.vp_create_obs(ctx, obs)
+    sh = vp.vp_create_sky(ctx, sky)
+    try:
+        with pytest.raises(vp.VPError) as ei:
+            vp.vp_peel(ctx, sh, oh, a1, a2, n_ant, n_iter, vp.VP_PREC_FP64, vp.VP_C128, d.data_ptr(), 0, 0)
+        assert ei.value.code == vp.VP_EINVAL
+    finally:
+        vp.vp_destroy_sky(sh)
+        vp.vp_destroy_obs(oh)
