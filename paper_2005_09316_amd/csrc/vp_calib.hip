@@ -18,11 +18,18 @@
 // at rounding level (a converged solve) has null-space components of its
 // own size that the iteration amplifies into a drift of the global phase.
 // The solve also stops once the residual is at the rounding level of r.
-// W (one value per tile pair, packed i < j) sits in LDS for the whole cell;
-// residuals are formed in FP64 from the data and model in global memory.
+// With X_ko = I^* V seen from tile k (a per-cell table built once), the
+// right-hand side is r_k = sum_o g_o X_ko - g_k D_k; X and W stream from
+// HBM once per Gauss-Newton iteration as full n x n tables, coalesced over
+// k.  For the conjugate-gradient products W sits in LDS, packed, in FP64
+// while it fits (up to 183 tiles) and in FP32 beyond: that changes the
+// step's operator at the 1e-7 level, not the right-hand side, so not the
+// fixed point.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "vp_internal.h"
 
@@ -49,28 +56,13 @@ __device__ __forceinline__ double2 load_vis(const void *p, int c64, int64_t i) {
   return ((const double2 *)p)[i];
 }
 
-// Sum of v over the workgroup (kTileRows threads); every thread gets the sum.
-__device__ __forceinline__ double block_sum(double v, double *red) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < kTileRows / 64; ++w) s += red[w];
-  return s;
-}
-
 // Removes from v (tile k's entry of a vector over tiles) its part along the
 // gauge direction i g of k's connected component:
 //   v <- v - i g_k (sum_{o in C} Im(g_o^* v_o)) / (sum_{o in C} |g_o|^2).
 // Sums run over the tiles in index order (deterministic); pv is LDS scratch.
-__device__ __forceinline__ double2 gauge_project(double2 v, double2 gk, int ck, bool own, int n,
+__device__ __forceinline__ double2 gauge_project(double2 v, double2 gk, int k, int ck, bool own, int n,
                                                  const int *comp, const double2 *g, double *pv) {
-  const int tid = threadIdx.x;
-  if (own) pv[tid] = ck >= 0 ? gk.x * v.y - gk.y * v.x : 0.0;
+  if (own) pv[k] = ck >= 0 ? gk.x * v.y - gk.y * v.x : 0.0;
   __syncthreads();
   if (own && ck >= 0) {
     double num = 0.0, den = 0.0;
@@ -90,113 +82,228 @@ __device__ __forceinline__ double2 gauge_project(double2 v, double2 gk, int ck, 
   return v;
 }
 
+// Per-cell tables for the solve, from the [T][B][K] model and data:
+//   xt [cell][o][k] = X_ko: I_b^* V_b for k = ant1, o = ant2 of baseline b,
+//                     its conjugate for k = ant2, o = ant1 (zero elsewhere:
+//                     the caller clears the table);
+//   wf [cell][o][k] = |I_b|^2 for both orders of the baseline's tiles
+//                     (zero elsewhere: the caller clears it too).
+// Consecutive threads take consecutive cells of one baseline, i.e. adjacent
+// channels: the reads are coalesced.
+__global__ __launch_bounds__(256) void k_gain_prep(GainArgs a) {
+  const int n = a.n_ant;
+  const int64_t total = (int64_t)a.ncell * a.B;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int cl = (int)(e % a.ncell), b = (int)(e / a.ncell);
+    const int cell = a.cell0 + cl, t = cell / a.K, kc = cell % a.K;
+    const int64_t i = ((int64_t)t * a.B + b) * a.K + kc;
+    const double2 m = load_vis(a.model, a.c64, i);
+    const double2 v = load_vis(a.data, a.c64, i);
+    const int i1 = a.ant1[b], i2 = a.ant2[b];
+    const double2 x = cmul(cconj(m), v);
+    double2 *xc = a.xt + (int64_t)cl * n * n;
+    xc[(int64_t)i2 * n + i1] = x;
+    xc[(int64_t)i1 * n + i2] = cconj(x);
+    double *wc = a.wf + (int64_t)cl * n * n;
+    const double w2 = m.x * m.x + m.y * m.y;
+    wc[(int64_t)i2 * n + i1] = w2;
+    wc[(int64_t)i1 * n + i2] = w2;
+  }
+}
+
+// Sums of two values over the workgroup in one pass.
+__device__ __forceinline__ double2 block_sum2(double u, double v, double2 *red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    u += __shfl_xor(u, o);
+    v += __shfl_xor(v, o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = make_double2(u, v);
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int w = 0; w < kGainThreads / 64; ++w) {
+    s.x += red[w].x;
+    s.y += red[w].y;
+  }
+  return s;
+}
+
+// Index of (i, j) in W packed with its (zero) diagonal: rows i of the upper
+// triangle j >= i, one after another.
+__device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
+  return i * n - i * (i - 1) / 2 + (j - i);
+}
+
+// One workgroup of kGainThreads threads per cell.  Thread (k, part) with
+// k = tid mod nk (nk = n rounded up to 64) and part = tid / nk sums over
+// the part-th slice o0 <= o < o1 of the tiles (wave-uniform); the part-0
+// thread of tile k holds the tile's gain and its conjugate-gradient state.
+// W sits in LDS packed with its zero diagonal, as WT.  The operator of the
+// step uses these W values for its diagonal too, so that i g stays its
+// exact null vector; the right-hand side uses the FP64 tables.  The solve
+// is conjugate gradients preconditioned by that diagonal (Jacobi).
 template <typename WT>
-__global__ __launch_bounds__(kTileRows) void k_gain_solve(GainArgs a) {
+__global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
   double2 *y = g + kPeelMaxAnt;                   // [kPeelMaxAnt] g_o p_o^* of the current direction
-  double *pv = (double *)(y + kPeelMaxAnt);       // [kPeelMaxAnt] projection scratch
+  double2 *pa = y + kPeelMaxAnt;                  // [kGainThreads] partial sums
+  double *pv = (double *)(pa + kGainThreads);     // [kPeelMaxAnt] projection scratch
   int *comp = (int *)(pv + kPeelMaxAnt);          // [kPeelMaxAnt] connected component of each tile
-  double *red = (double *)(comp + kPeelMaxAnt);   // [kTileRows / 64] reduction scratch
-  WT *W = (WT *)(red + 8);                        // [n_pairs] |I|^2 per tile pair
+  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [kGainThreads / 64] reduction scratch
+  WT *W = (WT *)(red + kGainThreads / 64);        // [n (n + 1) / 2] |I|^2, packed with the diagonal
 
-  const int cell = blockIdx.x;                    // t * K + k
+  const int cl = blockIdx.x, cell = a.cell0 + cl;
   const int t = cell / a.K, kc = cell % a.K;
   const int n = a.n_ant, tid = threadIdx.x;
-  const int npairs = n * (n - 1) / 2;
-  const int64_t base = (int64_t)t * a.B * a.K + kc;  // element (t, b, kc) at base + b K
+  const int nk = (n + 63) & ~63, parts = kGainThreads / nk;
+  const int k = tid % nk;
+  const int pt = __builtin_amdgcn_readfirstlane(tid / nk);  // nk is a multiple of 64: one part per wave
+  const int span = (n + parts - 1) / parts;
+  const int o0 = min(n, pt * span), o1 = min(n, o0 + span);
+  const bool row = k < n;                         // sums for tile k
+  const bool own = row && pt == 0;                // holds tile k's state
+  const int kr = row ? k : n - 1;                 // a valid row for the others (their sums are unused)
+  // W indices of (kr, o0): lower part (o < kr) and upper part (o >= kr)
+  const int pl0 = packed_index(n, o0 < kr ? o0 : 0, kr);
+  const int ph0 = packed_index(n, kr, o0 > kr ? o0 : kr);
 
-  for (int p = tid; p < npairs; p += kTileRows) {
-    const int b = a.pair_bl[p];
-    double w2 = 0.0;
-    if (b >= 0) {
-      const double2 m = load_vis(a.model, a.c64, base + (int64_t)b * a.K);
-      w2 = m.x * m.x + m.y * m.y;
-    }
-    W[p] = (WT)w2;
+  const double2 *X = a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
+  const double *Wf = a.wf + (int64_t)cl * n * n;  // |I|^2 [o n + k], FP64, zero for o == k
+  for (int idx = tid; idx < n * n; idx += kGainThreads) {
+    const int i = idx / n, j = idx - i * n;
+    if (i <= j) W[packed_index(n, i, j)] = (WT)Wf[idx];
   }
-  const bool own = tid < n;
   double2 gk = make_double2(1.0, 0.0);
-  const int ck = own ? a.comp[tid] : -1;
+  const int ck = own ? a.comp[k] : -1;
   if (own) {
-    g[tid] = gk;
-    comp[tid] = ck;
+    g[k] = gk;
+    comp[k] = ck;
   }
   __syncthreads();
 
-  for (int it = 0; it < a.n_iter; ++it) {
-    // right-hand side and diagonal for tile k
-    double2 r = make_double2(0.0, 0.0);
-    double D = 0.0, scale = 0.0;  // scale: sum of |terms| of r_k, for its rounding level
-    if (own) {
-      for (int o = 0; o < n; ++o) {
-        if (o == tid) continue;
-        const int p = tid < o ? pair_index(n, tid, o) : pair_index(n, o, tid);
-        const int b = a.pair_bl[p];
-        if (b < 0) continue;
-        const double2 go = g[o];
-        D += (go.x * go.x + go.y * go.y) * (double)W[p];
-        const double2 m = load_vis(a.model, a.c64, base + (int64_t)b * a.K);
-        const double2 v = load_vis(a.data, a.c64, base + (int64_t)b * a.K);
-        const bool first = a.ant1[b] == tid;  // this tile is ant1 of the baseline
-        const double2 gi = first ? gk : go, gj = first ? go : gk;
-        const double2 mdl = cmul(cmul(gi, cconj(gj)), m);
-        const double2 res = make_double2(v.x - mdl.x, v.y - mdl.y);
-        const double2 term = first ? cmul(go, cmul(cconj(m), res)) : cmul(go, cmul(m, cconj(res)));
-        r.x += term.x;
-        r.y += term.y;
-        scale += sqrt((go.x * go.x + go.y * go.y) * (m.x * m.x + m.y * m.y)) *
-                 (sqrt(v.x * v.x + v.y * v.y) + sqrt(mdl.x * mdl.x + mdl.y * mdl.y));
+  // sum over the slice of W_ko v_o (v in LDS); the diagonal term is zero
+  auto wdot = [&](const double2 *v, bool sq) {
+    double2 acc = make_double2(0.0, 0.0);
+    int pl = pl0, ph = ph0;
+#pragma unroll 4
+    for (int o = o0; o < o1; ++o) {
+      const bool lower = o < kr;
+      const int p = lower ? pl : ph;
+      pl += lower ? n - o - 1 : 0;
+      ph += lower ? 0 : 1;
+      const double wv = (double)W[p];
+      const double2 vo = v[o];
+      if (sq) {
+        acc.x += wv * (vo.x * vo.x + vo.y * vo.y);
+      } else {
+        acc.x += wv * vo.x;
+        acc.y += wv * vo.y;
       }
     }
-    r = gauge_project(r, gk, ck, own, n, comp, g, pv);
+    return acc;
+  };
+
+  for (int it = 0; it < a.n_iter; ++it) {
+    // r_k = sum_o g_o X_ko - g_k D_k,  D_k = sum_o W_ko |g_o|^2 in FP64;
+    // Dt_k: the same sum over the LDS copy of W
+    double2 sx = make_double2(0.0, 0.0);
+    double sd = 0.0, sa = 0.0;  // sa: sum of |g_o X_ko|, for the rounding level of r_k
+    if (row) {
+#pragma unroll 2
+      for (int o = o0; o < o1; ++o) {
+        const double2 go = g[o];
+        const double2 x = X[(int64_t)o * n + k];
+        const double g2 = go.x * go.x + go.y * go.y;
+        sx.x += go.x * x.x - go.y * x.y;
+        sx.y += go.x * x.y + go.y * x.x;
+        sa += sqrt(g2 * (x.x * x.x + x.y * x.y));
+        sd += g2 * Wf[(int64_t)o * n + k];
+      }
+    }
+    const double sdt = wdot(g, true).x;
+    double2 r = make_double2(0.0, 0.0);
+    double D = 0.0, Dt = 0.0, scale = 0.0;
+    // three rounds through the partial-sum buffer: (sx), (sd, sa), (sdt)
+    pa[tid] = sx;
+    __syncthreads();
+    if (own)
+      for (int q = 0; q < parts; ++q) {
+        r.x += pa[q * nk + k].x;
+        r.y += pa[q * nk + k].y;
+      }
+    __syncthreads();
+    pa[tid] = make_double2(sd, sa);
+    __syncthreads();
+    if (own)
+      for (int q = 0; q < parts; ++q) {
+        D += pa[q * nk + k].x;
+        scale += pa[q * nk + k].y;
+      }
+    __syncthreads();
+    pa[tid] = make_double2(sdt, 0.0);
+    __syncthreads();
+    if (own) {
+      for (int q = 0; q < parts; ++q) Dt += pa[q * nk + k].x;
+      r.x -= gk.x * D;
+      r.y -= gk.y * D;
+      scale += sqrt(gk.x * gk.x + gk.y * gk.y) * D;
+    }
+    const double minv = Dt > 0.0 ? 1.0 / Dt : 0.0;
+    r = gauge_project(r, gk, k, ck, own, n, comp, g, pv);
     // below this |r|^2 the right-hand side is rounding noise: no step
-    const double floor2 = kGainFloor * kGainFloor * block_sum(scale * scale, red);
-    // conjugate gradients on the normal equations, from e = 0
-    double2 x = make_double2(0.0, 0.0), res = r, pdir = r;
-    double rr = block_sum(res.x * res.x + res.y * res.y, red);
+    double2 x = make_double2(0.0, 0.0), res = r;
+    double2 z = make_double2(minv * r.x, minv * r.y), pdir = z;
+    const double2 s0 = block_sum2(res.x * res.x + res.y * res.y, scale * scale, red);
+    const double floor2 = kGainFloor * kGainFloor * s0.y;
+    double rr = s0.x, rz = block_sum2(res.x * z.x + res.y * z.y, 0.0, red).x;
     const double rr0 = rr;
     for (int cg = 0; cg < a.max_cg; ++cg) {
-      if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2)) break;
-      if (own) y[tid] = cmul(gk, cconj(pdir));
+      if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2) || !(rz > 0.0)) break;
+      if (own) y[k] = cmul(gk, cconj(pdir));
+      __syncthreads();
+      pa[tid] = wdot(y, false);
       __syncthreads();
       double2 q = make_double2(0.0, 0.0);
       if (own) {
         double2 s = make_double2(0.0, 0.0);
-        for (int o = 0; o < n; ++o) {
-          if (o == tid) continue;
-          const int p = tid < o ? pair_index(n, tid, o) : pair_index(n, o, tid);
-          const double wv = (double)W[p];
-          const double2 yo = y[o];
-          s.x += wv * yo.x;
-          s.y += wv * yo.y;
+        for (int j = 0; j < parts; ++j) {
+          const double2 v = pa[j * nk + k];
+          s.x += v.x;
+          s.y += v.y;
         }
         const double2 gs = cmul(gk, s);
-        q = make_double2(D * pdir.x + gs.x, D * pdir.y + gs.y);
+        q = make_double2(Dt * pdir.x + gs.x, Dt * pdir.y + gs.y);
       }
-      const double pq = block_sum(pdir.x * q.x + pdir.y * q.y, red);
+      const double pq = block_sum2(pdir.x * q.x + pdir.y * q.y, 0.0, red).x;
       if (!(pq > 0.0)) break;
-      const double alpha = rr / pq;
+      const double alpha = rz / pq;
       x.x += alpha * pdir.x;
       x.y += alpha * pdir.y;
       res.x -= alpha * q.x;
       res.y -= alpha * q.y;
-      const double rn = block_sum(res.x * res.x + res.y * res.y, red);
-      const double beta = rn / rr;
-      pdir = make_double2(res.x + beta * pdir.x, res.y + beta * pdir.y);
-      rr = rn;
+      z = make_double2(minv * res.x, minv * res.y);
+      const double2 s1 = block_sum2(res.x * res.x + res.y * res.y, res.x * z.x + res.y * z.y, red);
+      const double beta = s1.y / rz;
+      pdir = make_double2(z.x + beta * pdir.x, z.y + beta * pdir.y);
+      rr = s1.x;
+      rz = s1.y;
     }
-    x = gauge_project(x, gk, ck, own, n, comp, g, pv);
+    x = gauge_project(x, gk, k, ck, own, n, comp, g, pv);
     gk.x += x.x;
     gk.y += x.y;
-    __syncthreads();
-    if (own) g[tid] = gk;
+    if (own) g[k] = gk;
     __syncthreads();
   }
 
-  if (a.gains && own) a.gains[(int64_t)cell * n + tid] = gk;
+  if (a.gains && own) a.gains[(int64_t)cell * n + k] = gk;
   if (a.subtract) {
-    for (int b = tid; b < a.B; b += kTileRows) {
+    const int64_t base = (int64_t)t * a.B * a.K + kc;  // element (t, b, kc) at base + b K
+    for (int b = tid; b < a.B; b += kGainThreads) {
       const int64_t i = base + (int64_t)b * a.K;
       const double2 m = load_vis(a.model, a.c64, i);
       const double2 v = load_vis(a.data, a.c64, i);
@@ -210,28 +317,40 @@ __global__ __launch_bounds__(kTileRows) void k_gain_solve(GainArgs a) {
 }
 
 size_t gain_smem_bytes(int n_ant, bool w64) {
-  const size_t npairs = (size_t)n_ant * (n_ant - 1) / 2;
-  return kPeelMaxAnt * (2 * sizeof(double2) + sizeof(double) + sizeof(int)) + 8 * sizeof(double) +
-         npairs * (w64 ? sizeof(double) : sizeof(float));
+  const size_t packed = (size_t)n_ant * (n_ant + 1) / 2;
+  return kPeelMaxAnt * (2 * sizeof(double2) + sizeof(double) + sizeof(int)) + kGainThreads * sizeof(double2) +
+         (kGainThreads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
 }
 
+bool gain_supported(int n_ant) {
+  return n_ant >= 2 && n_ant <= kPeelMaxAnt && gain_smem_bytes(n_ant, false) <= kPeelSmemMax;
+}
+
+size_t gain_cell_bytes(int n_ant) { return (size_t)n_ant * n_ant * (sizeof(double2) + sizeof(double)); }
+
 hipError_t launch_gain(const GainArgs &a, hipStream_t s) {
-  const int64_t cells = (int64_t)a.T * a.K;
-  if (cells <= 0) return hipSuccess;
-  if (cells > 0x7fffffff || a.n_ant < 2 || a.n_ant > kPeelMaxAnt) return hipErrorInvalidValue;
+  if (a.ncell <= 0) return hipSuccess;
+  if (!gain_supported(a.n_ant) || a.cell0 < 0 || (int64_t)a.cell0 + a.ncell > (int64_t)a.T * a.K)
+    return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(a.xt, 0, (size_t)a.ncell * a.n_ant * a.n_ant * sizeof(double2), s);
+  if (e == hipSuccess) e = hipMemsetAsync(a.wf, 0, (size_t)a.ncell * a.n_ant * a.n_ant * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)a.ncell * a.B;
+  const unsigned prep_blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_gain_prep, dim3(prep_blocks), dim3(256), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)a.ncell), block(kGainThreads);
   const bool w64 = gain_smem_bytes(a.n_ant, true) <= kPeelSmemMax;
   const size_t sm = gain_smem_bytes(a.n_ant, w64);
-  if (sm > kPeelSmemMax) return hipErrorInvalidValue;
   if (w64) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    e = hipFuncSetAttribute((const void *)k_gain_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gain_solve<double>, dim3((unsigned)cells), dim3(kTileRows), sm, s, a);
+    hipLaunchKernelGGL(k_gain_solve<double>, grid, block, sm, s, a);
   } else {
-    hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    e = hipFuncSetAttribute((const void *)k_gain_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gain_solve<float>, dim3((unsigned)cells), dim3(kTileRows), sm, s, a);
+    hipLaunchKernelGGL(k_gain_solve<float>, grid, block, sm, s, a);
   }
   return hipGetLastError();
 }

@@ -151,6 +151,8 @@ constexpr int kProfClasses = 4;
 // Peel calibration (vp_calib.hip).
 constexpr int kPeelMaxAnt = 256;          // tiles per observation (one thread each)
 constexpr size_t kPeelSmemMax = 163840;  // LDS per workgroup on gfx950
+constexpr int kGainThreads = 1024;       // threads per cell of the gain solve
+constexpr size_t kPeelWsMax = size_t(1) << 30;  // per-cell tables of one launch, bytes (at least one cell)
 
 struct GainArgs {
   int T, B, K;            // cells are (time, channel); B baselines per time step
@@ -164,6 +166,9 @@ struct GainArgs {
   const int32_t *comp;         // [n_ant] connected component of each tile in the baseline graph, -1 if idle
   double2 *gains;         // [T][K][n_ant] output, or null
   int subtract;
+  int cell0, ncell;       // the launch covers cells cell0 .. cell0 + ncell - 1 (cell = t K + k)
+  double2 *xt;            // workspace [ncell][n_ant][n_ant]
+  double *wf;             // workspace [ncell][n_ant][n_ant]
 };
 
 // Host-side launchers (vp_kernels.hip).
@@ -176,7 +181,9 @@ hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks,
                         hipStream_t s);
 hipError_t serve_grid(int *grid);
 hipError_t launch_gain(const GainArgs &a, hipStream_t s);
+bool gain_supported(int n_ant);
 size_t gain_smem_bytes(int n_ant, bool w64);
+size_t gain_cell_bytes(int n_ant);  // workspace bytes per cell
 
 // sizes of per-shapelet tile storage
 inline int64_t a32_floats(int nmax) { return (int64_t)shp_pairs(nmax) * kA32PerPair; }

@@ -33,8 +33,10 @@ struct PeelWork {
   DeviceMem mem;
   void *model = nullptr;
   size_t model_bytes = 0;
-  int32_t *tab = nullptr;  // ant1 [B], ant2 [B], pair_bl [n_pairs]
+  int32_t *tab = nullptr;  // ant1 [B], ant2 [B], pair_bl [n_pairs], comp [n_ant]
   size_t tab_n = 0;
+  void *ws = nullptr;      // per-cell tables of the gain solve
+  size_t ws_bytes = 0;
   hipEvent_t done = nullptr;
 };
 

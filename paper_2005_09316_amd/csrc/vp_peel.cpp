@@ -25,6 +25,7 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   if (n_iter < 0 || n_iter > VP_PEEL_MAX_ITER)
     return set_error(VP_EINVAL, "n_iter %d outside 0..%d", n_iter, VP_PEEL_MAX_ITER);
   const int B = obs->B;
+  if ((int64_t)obs->T * obs->K > 0x7fffffff) return set_error(VP_EINVAL, "too many (time, channel) cells");
   const int npairs = n_ant * (n_ant - 1) / 2;
   // tables: ant1 [B], ant2 [B], baseline of each tile pair [npairs], and
   // the connected component of each tile [n_ant] (-1: no baseline)
@@ -57,7 +58,7 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
     int32_t *comp = tab.data() + 2 * (size_t)B + npairs;
     for (int k = 0; k < n_ant; ++k) comp[k] = used[k] ? root(k) : -1;
   }
-  if (gain_smem_bytes(n_ant, false) > kPeelSmemMax) return set_error(VP_EINVAL, "too many tiles");
+  if (!gain_supported(n_ant)) return set_error(VP_EINVAL, "%d tiles not supported by the gain solve", n_ant);
   DeviceGuard g(ctx->device);
   if (!g.ok) return set_error(VP_EDEVICE, "cannot select device");
   {
@@ -71,19 +72,25 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   if (w.done) e = hipEventSynchronize(w.done);
   if (e != hipSuccess) return hip_error(e, "waiting for the previous peel");
   const size_t mbytes = (size_t)obs->T * B * obs->K * (dtype == VP_C64 ? 8 : 16);
-  if (mbytes > w.model_bytes || tab.size() > w.tab_n) {
+  const int64_t cells = (int64_t)obs->T * obs->K;
+  const size_t cell_bytes = gain_cell_bytes(n_ant);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(cells, (int64_t)(kPeelWsMax / cell_bytes)));
+  const size_t wsbytes = (size_t)chunk * cell_bytes;
+  if (mbytes > w.model_bytes || tab.size() > w.tab_n || wsbytes > w.ws_bytes) {
     w.mem.release();
-    w.model = nullptr;
+    w.model = w.ws = nullptr;
     w.tab = nullptr;
     w.model_bytes = std::max(mbytes, w.model_bytes);
     w.tab_n = std::max(tab.size(), w.tab_n);
+    w.ws_bytes = std::max(wsbytes, w.ws_bytes);
     e = w.mem.alloc(&w.model, w.model_bytes);
     if (e == hipSuccess) e = w.mem.alloc((void **)&w.tab, sizeof(int32_t) * w.tab_n);
+    if (e == hipSuccess) e = w.mem.alloc(&w.ws, w.ws_bytes);
     if (e != hipSuccess) {
       w.mem.release();
-      w.model = nullptr;
+      w.model = w.ws = nullptr;
       w.tab = nullptr;
-      w.model_bytes = w.tab_n = 0;
+      w.model_bytes = w.tab_n = w.ws_bytes = 0;
       return hip_error(e, "allocating the peel workspace");
     }
   }
@@ -109,9 +116,15 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   a.comp = a.pair_bl + npairs;
   a.gains = (double2 *)gains_dev;
   a.subtract = 1;
+  a.xt = (double2 *)w.ws;
+  a.wf = (double *)((char *)w.ws + (size_t)chunk * n_ant * n_ant * sizeof(double2));
   {
     ProfScope ps(ctx, s, 3);
-    e = launch_gain(a, s);
+    for (int64_t c0 = 0; c0 < cells && e == hipSuccess; c0 += chunk) {
+      a.cell0 = (int)c0;
+      a.ncell = (int)std::min<int64_t>(chunk, cells - c0);
+      e = launch_gain(a, s);
+    }
   }
   if (e != hipSuccess) return hip_error(e, "launching the gain solve");
   if (!w.done) e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming);
