@@ -215,7 +215,7 @@ def truncation_sweep(check_rows=8, fracs=(1.0, 0.95, 0.9, 0.8, 0.7, 0.5), orders
     return res
 
 
-def calibrated_peel(n_iter=8, check_chan=(17,)):
+def calibrated_peel(n_iter=10, check_chan=(17,)):
     """Workload 4's observation: data = sum over the 10 shapelet sources of
     g_i g_j^* V_s (a gain table of its own per source) + N(0, 1 Jy) noise,
     complex64, resident.  Timed: the 10 vp_peel calls in sequence (predict
