@@ -71,6 +71,11 @@ extern "C" {
 #define VP_PREC_MIXED_BF16X2 4 /* as MIXED, contraction as 2-way BF16 split (3 products; reported) */
 #define VP_PREC_MIXED_F32MMA 5 /* as MIXED, contraction on FP32 MFMA folded into FP64 every 8 orders
                                   (reported: ~1e-6 of total flux on heavily cancelling coefficients) */
+#define VP_PREC_LUT 6         /* as FP64, but the shapelet basis read from a 1-D FP32 table of the
+                                 Hermite functions (8192 samples over 0 <= x < 32, linear
+                                 interpolation), as the paper's simulator does (Sec. 3.2);
+                                 for comparison (reported, not accurate); built per context at
+                                 first use (400 x 8194 floats) */
 
 /* output element types */
 #define VP_C128 0

@@ -254,11 +254,35 @@ ProfScope::~ProfScope() { end(); }
 // predict / subtract
 // ---------------------------------------------------------------------------
 
+// The basis table of the lookup-table variant, built once per context (the
+// build is synchronous: later calls on any stream find it complete).
+static int get_lut(vp_ctx *ctx, hipStream_t stream, const float **out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->lut) {
+    void *p = nullptr;
+    hipError_t e = ctx->lut_mem.alloc(&p, kLutBytes);
+    if (e == hipSuccess) e = launch_lut_build((float *)p, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      ctx->lut_mem.release();
+      return hip_error(e, "building the basis lookup table");
+    }
+    ctx->lut = (float *)p;
+  }
+  *out = ctx->lut;
+  return VP_OK;
+}
+
 int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis,
               int subtract, hipStream_t stream) {
   DerivedEntry *d = nullptr;
   int rc = get_derived(ctx, sky, obs, stream, &d);
   if (rc != VP_OK) return rc;
+  const float *lut = nullptr;
+  if (precision == kLut && sky->S > 0) {
+    rc = get_lut(ctx, stream, &lut);
+    if (rc != VP_OK) return rc;
+  }
   TileArgs a;
   a.nrows = (int64_t)obs->T * obs->B;
   a.K = obs->K;
@@ -275,6 +299,7 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.nb = 0;
   a.n_rb = (int)((a.nrows + kTileRows - 1) / kTileRows);
   a.n_cb = obs->Kpad / kPgChan;
+  a.lut = lut;
   hipError_t e;
   {
     ProfScope ps(ctx, stream, 1);
@@ -294,7 +319,7 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
 int check_call(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis) {
   if (!ctx || !sky || !obs) return set_error(VP_EINVAL, "NULL context, sky or observation");
   if (sky->ctx != ctx || obs->ctx != ctx) return set_error(VP_EINVAL, "sky or observation belongs to another context");
-  if (precision < VP_PREC_FP64 || precision > VP_PREC_MIXED_F32MMA)
+  if (precision < VP_PREC_FP64 || precision > VP_PREC_LUT)
     return set_error(VP_EINVAL, "unknown precision %d", precision);
   if (dtype != VP_C128 && dtype != VP_C64) return set_error(VP_EINVAL, "unknown dtype %d", dtype);
   if (!vis) return set_error(VP_EINVAL, "NULL visibility buffer");
@@ -363,6 +388,7 @@ int vp_destroy_ctx(vp_ctx *ctx) {
     ctx->peel->mem.release();
     delete ctx->peel;
   }
+  ctx->lut_mem.release();
   delete ctx;
   return VP_OK;
 }

@@ -32,7 +32,14 @@ constexpr int kPairsMax = (kNmaxLimit / 32 + 1) * (kNmaxLimit / 32 + 2) / 2;
 constexpr int kA32PerPair = 2 * 8 * 64;  // floats: [parity][K step of 2 orders][lane]
 constexpr int kAbfPerPair = 2 * 64 * 8;  // BF16 values of one split part: [parity][lane][8]
 
-enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4, kMixedF32Mma = 5 };
+enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4, kMixedF32Mma = 5, kLut = 6 };
+
+// Lookup table of the basis (the lookup-table variant): kLutSamples + 2 rows
+// of kLutStride FP32 values.
+constexpr int kLutSamples = 8192;
+constexpr double kLutXMax = 32.0;
+constexpr int kLutStride = 100;
+constexpr size_t kLutBytes = (size_t)(kLutSamples + 2) * kLutStride * sizeof(float);
 
 // Per-(sky, observation) tables, built on the device.  Plain aggregates (no
 // member initialisers) so that they can live in LDS inside the serving kernel.
@@ -105,6 +112,7 @@ struct TileArgs {
   int c64;             // 1: complex64, 0: complex128
   int conj;            // 1 when the exponent sign is -1
   int nb;              // FP64 shapelet kernel: order bucket
+  const float *lut;    // basis table of the lookup-table variant, or null
 };
 
 // ---------------------------------------------------------------------------
@@ -177,6 +185,7 @@ hipError_t launch_flux(const FluxArgs &a, hipStream_t s);
 hipError_t launch_tiles_build(const TileBuildArgs &a, int max_nmax, hipStream_t s);
 hipError_t launch_pg(const TileArgs &a, int prec, hipStream_t s);
 hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s);
+hipError_t launch_lut_build(float *T, hipStream_t s);
 hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
                         hipStream_t s);
 hipError_t serve_grid(int *grid);

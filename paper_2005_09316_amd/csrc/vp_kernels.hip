@@ -25,7 +25,8 @@
 //               skipped), finish the n1 sum against the first axis in the
 //               MFMA output layout, and add flux x envelope x phase into a
 //               Kahan accumulator held in LDS.
-//   k_shp_fp64  the FP64 path of the shapelet term on the vector ALU.
+//   k_shp_fp64  the FP64 path of the shapelet term on the vector ALU (and
+//               the lookup-table variant of the basis).
 //
 // All arithmetic is done with the exponent sign +1; a sign of -1 is applied
 // by conjugating at the output, which is exact.
@@ -876,7 +877,55 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
 // Hermite values live in registers (NB + 1 of them, NB the order bucket), the
 // first axis's recurrence advances with the n1 loop, and each n1 row of the
 // signed coefficient matrix is read as wave-uniform loads.
-template <int NB>
+// Lookup-table variant of the basis (the paper's simulator interpolates a
+// 1-D table of the basis, Sec. 3.2): phi_n at x_i = i dx, 0 <= i <= kLutSamples,
+// dx = kLutXMax / kLutSamples, FP32, rows of kLutStride orders; phi_n(-x) =
+// (-1)^n phi_n(x) covers x < 0 and the table reads zero beyond kLutXMax
+// (phi_96(32) ~ 1e-78).  Built once per context from the FP64 recurrence.
+__global__ __launch_bounds__(256) void k_lut_build(float *T) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > kLutSamples + 1) return;
+  const double x = i * (kLutXMax / kLutSamples);
+  const double sx = 1.41421356237309504880 * x;
+  double p = kPiM14 * exp(-0.5 * x * x), pm1 = 0.0;
+  float *row = T + (int64_t)i * kLutStride;
+  for (int n = 0; n < kLutStride; ++n) {
+    row[n] = n <= kNmaxLimit ? (float)p : 0.0f;
+    if (n < kNmaxLimit) {
+      const double nx = herm_step<double>(sx, p, pm1, n);
+      pm1 = p;
+      p = nx;
+    }
+  }
+}
+
+// Interpolation position in the table: row pointer, fraction and the sign
+// of odd orders.
+struct LutPos {
+  const float *r0;
+  float fr, odd;
+  bool in;
+};
+
+__device__ __forceinline__ LutPos lut_pos(const float *T, double x) {
+  LutPos q;
+  const double t = fabs(x) * (kLutSamples / kLutXMax);
+  q.in = t < (double)kLutSamples;
+  const int i = q.in ? (int)t : 0;
+  q.fr = q.in ? (float)(t - i) : 0.0f;
+  q.r0 = T + (int64_t)i * kLutStride;
+  q.odd = x < 0.0 ? -1.0f : 1.0f;
+  return q;
+}
+
+__device__ __forceinline__ double lut_at(const LutPos &q, int n) {
+  if (!q.in) return 0.0;
+  const float v0 = q.r0[n], v1 = q.r0[n + kLutStride];
+  const float v = fmaf(q.fr, v1 - v0, v0);
+  return (double)((n & 1) ? q.odd * v : v);
+}
+
+template <int NB, bool LUT>
 __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
   constexpr int KB = kShpChan;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -899,7 +948,11 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
       const double xb = f * fma(fr[3], u, fma(fr[4], v, fr[5] * w));
       const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
       double pb[NB + 8];
-      {
+      if constexpr (LUT) {
+        const LutPos qb = lut_pos(a.lut, xb);
+#pragma unroll
+        for (int n = 0; n < NB + 8; ++n) pb[n] = n <= kNmaxLimit ? lut_at(qb, n) : 0.0;
+      } else {
         const double sx = 1.41421356237309504880 * xb;
         pb[0] = kPiM14 * exp(-0.5 * xb * xb);
         double pm1 = 0.0;
@@ -914,6 +967,11 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
       const int ld = a.t.c64_ld[j];
       const double sx = 1.41421356237309504880 * xa;
       double pa = kPiM14 * exp(-0.5 * xa * xa), pam1 = 0.0;
+      LutPos qa;
+      if constexpr (LUT) {
+        qa = lut_pos(a.lut, xa);
+        pa = lut_at(qa, 0);
+      }
       double xr = 0.0, xi = 0.0;
       for (int n1 = 0; n1 <= N; ++n1) {
         const double *Cr = C + (int64_t)n1 * ld;
@@ -935,9 +993,13 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
           xr = fma(pa, te, xr);
           xi = fma(pa, to, xi);
         }
-        const double nx = herm_step<double>(sx, pa, pam1, n1);
-        pam1 = pa;
-        pa = nx;
+        if constexpr (LUT) {
+          pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
+        } else {
+          const double nx = herm_step<double>(sx, pa, pam1, n1);
+          pam1 = pa;
+          pa = nx;
+        }
       }
       double cs, sn;
       turns_sincos_f64(t0 * f, cs, sn);
@@ -1216,13 +1278,24 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) 
   switch (prec) {
     case kFP64:
       if (max_nmax <= 16)
-        hipLaunchKernelGGL(k_shp_fp64<16>, g, b, 0, s, a);
+        hipLaunchKernelGGL((k_shp_fp64<16, false>), g, b, 0, s, a);
       else if (max_nmax <= 32)
-        hipLaunchKernelGGL(k_shp_fp64<32>, g, b, 0, s, a);
+        hipLaunchKernelGGL((k_shp_fp64<32, false>), g, b, 0, s, a);
       else if (max_nmax <= 64)
-        hipLaunchKernelGGL(k_shp_fp64<64>, g, b, 0, s, a);
+        hipLaunchKernelGGL((k_shp_fp64<64, false>), g, b, 0, s, a);
       else
-        hipLaunchKernelGGL(k_shp_fp64<96>, g, b, 0, s, a);
+        hipLaunchKernelGGL((k_shp_fp64<96, false>), g, b, 0, s, a);
+      break;
+    case kLut:
+      if (!a.lut) return hipErrorInvalidValue;
+      if (max_nmax <= 16)
+        hipLaunchKernelGGL((k_shp_fp64<16, true>), g, b, 0, s, a);
+      else if (max_nmax <= 32)
+        hipLaunchKernelGGL((k_shp_fp64<32, true>), g, b, 0, s, a);
+      else if (max_nmax <= 64)
+        hipLaunchKernelGGL((k_shp_fp64<64, true>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_shp_fp64<96, true>), g, b, 0, s, a);
       break;
     case kFP32:
       hipLaunchKernelGGL((k_shp_mfma<float, float, kCmF32>), g, b, 0, s, a);
@@ -1240,6 +1313,13 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) 
     default:
       return hipErrorNotSupported;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_lut_build(float *T, hipStream_t s) {
+  hipError_t e = upload_tables();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lut_build, dim3((kLutSamples + 2 + 255) / 256), dim3(256), 0, s, T);
   return hipGetLastError();
 }
 

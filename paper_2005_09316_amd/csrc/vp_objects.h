@@ -146,4 +146,6 @@ struct vp_ctx {
   std::vector<vp::ProfRecord> prof_pending;
   vp::Scheduler *sched = nullptr;
   vp::PeelWork *peel = nullptr;
+  float *lut = nullptr;    // basis table of VP_PREC_LUT, built at its first use (guarded by mu)
+  vp::DeviceMem lut_mem;
 };

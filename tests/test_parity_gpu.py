@@ -211,3 +211,44 @@ def test_effective_order_and_truncation(ctx):
     err = oracle.error_metric(got, oracle.predict(obs, tf), obs, tf)
     _log("flux-truncated model (%d of %d kept): error / total flux = %.3e" % (n, ntot, err))
     assert err <= 1e-6
+
+
+def test_lookup_table_variant_within_interpolation_bound(ctx):
+    """VP_PREC_LUT reads the basis from an FP32 table of phi_n on a uniform
+    grid of step h = 32/8192 with linear interpolation (the paper's
+    simulator's evaluation, Sec. 3.2).  Bound from the oracle's Hermite
+    functions: the interpolation error of phi_n is at most
+    h^2/8 max|phi_n''| with phi_n'' = (x^2 - 2n - 1) phi_n, plus FP32
+    rounding of the table and the interpolation (3 * 2^-24 * pi^(-1/4));
+    with e = the largest of these over the orders used and M = pi^(-1/4)
+    (|phi_n| <= M), each shapelet's envelope moves by at most
+    sum |C| (2 e M + e^2), and the flux-weighted sum of that over the
+    shapelets, against the total flux, bounds the error metric."""
+    obs, sky = synth.make_config(0, n_tiles=16, n_time=2, n_chan=3, n_point=2, n_gauss=1,
+                                 shapelet_nmax=[30, 12])
+    nmax = int(max(sky.s_nmax))
+    h = 32.0 / 8192
+    xs = np.linspace(0.0, 32.0, 4001)
+    phi = np.array([oracle.hermite(nmax, x) for x in xs])           # [x][n]
+    n = np.arange(nmax + 1)
+    d2 = np.abs((xs[:, None] ** 2 - 2 * n[None, :] - 1) * phi).max()
+    M = math.pi ** -0.25
+    e = h * h / 8.0 * d2 + 3 * 2.0 ** -24 * M
+    ft = np.abs(oracle.flux_table(obs, sky))                        # [J][K]
+    j0 = sky.n_point + sky.n_gauss
+    bound_abs = np.zeros(obs.n_chan)
+    for s in range(sky.n_shp):
+        N = int(sky.s_nmax[s])
+        c = sky.coeffs[int(sky.s_coeff_off[s]):int(sky.s_coeff_off[s]) + (N + 1) * (N + 2) // 2]
+        bound_abs += ft[j0 + s] * np.abs(c).sum() * (2 * e * M + e * e)
+    bound = float((bound_abs / oracle.total_flux(obs, sky)).max())
+    ref = oracle.predict(obs, sky)
+    with Handles(ctx, obs, sky) as hd:
+        got = run(ctx, hd.obs, hd.sky, obs, vp.VP_PREC_LUT, vp.VP_C128)
+        exact = run(ctx, hd.obs, hd.sky, obs, vp.VP_PREC_FP64, vp.VP_C128)
+    err = oracle.error_metric(got, ref, obs, sky)
+    err64 = oracle.error_metric(exact, ref, obs, sky)
+    _log("lookup-table basis: error / total flux %.3e (bound %.3e); recurrence %.3e" % (err, bound, err64))
+    assert np.all(np.isfinite(got))
+    assert err <= bound
+    assert err64 <= TOL[vp.VP_PREC_FP64]
