@@ -87,6 +87,7 @@ extern "C" {
 
 /* maximum shapelet order n1 + n2 */
 #define VP_NMAX_LIMIT 96
+#define VP_NTERM_LIMIT 8      /* spectral terms per shapelet */
 #define VP_PEEL_MAX_ANT 256   /* tiles a peel can calibrate (one thread per tile) */
 #define VP_PEEL_MAX_ITER 1000 /* Gauss-Newton iterations accepted by vp_peel */
 #define VP_PEEL_MAX_CG 200    /* conjugate-gradient steps per Gauss-Newton step (bound) */
@@ -108,7 +109,14 @@ typedef struct {
 
 /* Sky model (Sec. 3.1 points; Sec. 3.2 Gaussians and shapelets; Sec. 4.1 spectra).
  * Shapelet coefficients are packed per shapelet, n1-major: n1 = 0..N, then
- * n2 = 0..N-n1, (N+1)(N+2)/2 values starting at coeffs[s_coeff_off[s]]. */
+ * n2 = 0..N-n1, (N+1)(N+2)/2 values starting at coeffs[s_coeff_off[s]].
+ * Frequency-dependent coefficients (the fit of the coefficients as a function
+ * of frequency that Sec. 7 proposes, letting the spectral index vary across a
+ * source): with s_nterm non-NULL, shapelet s has Q = s_nterm[s] blocks
+ * C_0 .. C_{Q-1} of (N+1)(N+2)/2 values one after another from
+ * coeffs[s_coeff_off[s]], and its coefficients at frequency nu are
+ * C(nu) = sum_q C_q ln(nu / nu_ref_hz)^q (still multiplied by the power-law
+ * flux).  Each term costs one shapelet's work. */
 typedef struct {
   double nu_ref_hz; /* reference frequency of S_ref */
   int32_t n_point;
@@ -122,6 +130,7 @@ typedef struct {
   const int32_t *s_nmax;                  /* N = max(n1 + n2) per shapelet, 0..VP_NMAX_LIMIT */
   const int64_t *s_coeff_off;             /* offset of each shapelet's coefficients */
   const double *coeffs;
+  const int32_t *s_nterm;                 /* NULL (one term each) or [n_shp] 1..VP_NTERM_LIMIT */
 } vp_sky_desc;
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes bounds the
@@ -151,7 +160,8 @@ int vp_destroy_obs(vp_obs *obs); /* VP_EBUSY while a pending job uses it */
  * scattered coefficients does not).  Errors: VP_EINVAL for
  * negative counts, NULL arrays with a positive count, non-finite values,
  * nu_ref <= 0, Gaussian FWHM < 0, beta <= 0, nmax outside 0..VP_NMAX_LIMIT,
- * coefficient offsets < 0; VP_ENOMEM; VP_EDEVICE. */
+ * coefficient offsets < 0, spectral terms outside 1..VP_NTERM_LIMIT; VP_ENOMEM;
+ * VP_EDEVICE. */
 int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *desc, vp_sky **out);
 int vp_destroy_sky(vp_sky *sky); /* VP_EBUSY while a pending job uses it */
 

@@ -30,6 +30,7 @@ Every function here is pinned by a test in ``tests/test_oracle_pins.py``.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional
@@ -64,6 +65,7 @@ class _Sky(ctypes.Structure):
         ("n_shp", ctypes.c_int32), ("s_ra", _dp), ("s_dec", _dp), ("s_sref", _dp), ("s_alpha", _dp),
         ("s_beta1", _dp), ("s_beta2", _dp), ("s_pa", _dp),
         ("s_nmax", _i32p), ("s_coeff_off", _i64p), ("coeffs", _dp),
+        ("s_nterm", _i32p),
     ]
 
 
@@ -137,7 +139,12 @@ def _marshal(obs, sky, sign: Optional[int] = None):
              f(sky.g_maj), f(sky.g_min), f(sky.g_pa),
              int(np.size(sky.s_ra)), f(sky.s_ra), f(sky.s_dec), f(sky.s_sref), f(sky.s_alpha),
              f(sky.s_beta1), f(sky.s_beta2), f(sky.s_pa),
-             _ptr(nmax, _i32p), _ptr(off, _i64p), f(sky.coeffs))
+             _ptr(nmax, _i32p), _ptr(off, _i64p), f(sky.coeffs), None)
+    nterm = getattr(sky, "s_nterm", None)
+    if nterm is not None:
+        nt = np.ascontiguousarray(np.asarray(nterm, np.int32))
+        keep.append(nt)
+        s.s_nterm = _ptr(nt, _i32p)
     return o, s, keep
 
 
@@ -227,24 +234,32 @@ def flux_table(obs, sky) -> np.ndarray:
     return out[:J]
 
 
-def xi_origin(sky) -> np.ndarray:
+def xi_origin(sky, nu_hz=None) -> np.ndarray:
     """|xi_j(0)| per component: 1 for points and Gaussians, the shapelet
-    envelope at the uv origin otherwise."""
+    envelope at the uv origin otherwise (with spectral terms, of the
+    coefficients at frequency nu_hz, default the reference frequency)."""
     vals = [1.0] * int(np.size(sky.p_ra) + np.size(sky.g_ra))
+    nterm = getattr(sky, "s_nterm", None)
+    x = 0.0 if nu_hz is None else math.log(nu_hz / sky.nu_ref_hz)
     for s in range(int(np.size(sky.s_ra))):
         n = int(sky.s_nmax[s])
         o = int(sky.s_coeff_off[s])
-        c = np.asarray(sky.coeffs[o:o + (n + 2) * (n + 1) // 2])
+        cnt = (n + 2) * (n + 1) // 2
+        q_n = 1 if nterm is None else int(nterm[s])
+        c = sum(np.asarray(sky.coeffs[o + q * cnt:o + (q + 1) * cnt]) * x ** q for q in range(q_n))
         vals.append(abs(shapelet_envelope_ab(n, c, 0.0, 0.0)))
     return np.asarray(vals, np.float64)
 
 
 def total_flux(obs, sky) -> np.ndarray:
-    """F_k = sum_j |S_j(nu_k)| |xi_j(0)|, shape [K]."""
+    """F_k = sum_j |S_j(nu_k)| |xi_j(0)|, shape [K] (xi_j(0) at nu_k when a
+    shapelet has spectral terms)."""
     ft = flux_table(obs, sky)
     if ft.shape[0] == 0:
         return np.zeros(int(obs.n_chan))
-    return np.abs(ft).T @ xi_origin(sky)
+    if getattr(sky, "s_nterm", None) is None:
+        return np.abs(ft).T @ xi_origin(sky)
+    return np.array([np.abs(ft[:, k]) @ xi_origin(sky, float(obs.freq_hz[k])) for k in range(int(obs.n_chan))])
 
 
 def error_metric(v, v_ref, obs, sky) -> float:

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #define ORACLE_NMAX_CAP 255
+#define ORACLE_NTERM_CAP 16
 
 typedef struct {
   int32_t n_time, n_bl, n_chan;
@@ -28,6 +29,11 @@ typedef struct {
   const int32_t *s_nmax;
   const int64_t *s_coeff_off;
   const double *coeffs;
+  /* NULL, or [n_shp] numbers of spectral terms: shapelet s's coefficients at
+   * frequency nu are C(nu) = sum_{q < s_nterm[s]} C_q ln(nu / nu_ref)^q, the
+   * blocks C_q of (N+1)(N+2)/2 values following each other from
+   * coeffs[s_coeff_off[s]] */
+  const int32_t *s_nterm;
 } oracle_sky;
 
 void oracle_hermite(int32_t nmax, double x, double *phi);

@@ -113,6 +113,8 @@ FluxArgs make_flux_args(const vp_sky *sky, const vp_obs *obs, const Derived &d) 
   fa.sref = sky->sref; fa.alpha = sky->alpha; fa.ra = sky->ra; fa.dec = sky->dec; fa.freq = obs->freq;
   fa.nu_ref = sky->nu_ref; fa.ra0 = obs->ra0; fa.dec0 = obs->dec0;
   fa.beam_fwhm = obs->beam_fwhm; fa.beam_nu_ref = obs->beam_nu_ref;
+  fa.j0 = sky->P + sky->G;
+  fa.lpow = sky->lpow;
   fa.d = d;
   return fa;
 }
@@ -461,13 +463,13 @@ int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *d, vp_sky **out) {
   if (!ctx || !d || !out) return set_error(VP_EINVAL, "NULL argument");
   if (d->n_point < 0 || d->n_gauss < 0 || d->n_shp < 0) return set_error(VP_EINVAL, "negative component count");
   if (!(d->nu_ref_hz > 0) || !std::isfinite(d->nu_ref_hz)) return set_error(VP_EINVAL, "nu_ref must be positive");
-  const int P = d->n_point, G = d->n_gauss, S = d->n_shp;
-  if ((int64_t)P + G + S > (1 << 28)) return set_error(VP_EINVAL, "too many components");
+  const int P = d->n_point, G = d->n_gauss, Sd = d->n_shp;
+  if ((int64_t)P + G + Sd > (1 << 28)) return set_error(VP_EINVAL, "too many components");
   if (P > 0 && (!d->p_ra || !d->p_dec || !d->p_sref || !d->p_alpha)) return set_error(VP_EINVAL, "NULL point array");
   if (G > 0 && (!d->g_ra || !d->g_dec || !d->g_sref || !d->g_alpha || !d->g_maj || !d->g_min || !d->g_pa))
     return set_error(VP_EINVAL, "NULL Gaussian array");
-  if (S > 0 && (!d->s_ra || !d->s_dec || !d->s_sref || !d->s_alpha || !d->s_beta1 || !d->s_beta2 || !d->s_pa ||
-                !d->s_nmax || !d->s_coeff_off || !d->coeffs))
+  if (Sd > 0 && (!d->s_ra || !d->s_dec || !d->s_sref || !d->s_alpha || !d->s_beta1 || !d->s_beta2 || !d->s_pa ||
+                 !d->s_nmax || !d->s_coeff_off || !d->coeffs))
     return set_error(VP_EINVAL, "NULL shapelet array");
   const double *pa[] = {d->p_ra, d->p_dec, d->p_sref, d->p_alpha};
   for (auto p : pa)
@@ -479,27 +481,46 @@ int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *d, vp_sky **out) {
     if (d->g_maj[g] < 0 || d->g_min[g] < 0) return set_error(VP_EINVAL, "Gaussian %d has a negative FWHM", g);
   const double *sa[] = {d->s_ra, d->s_dec, d->s_sref, d->s_alpha, d->s_beta1, d->s_beta2, d->s_pa};
   for (auto p : sa)
-    if (S > 0 && !finite_all(p, S)) return set_error(VP_EINVAL, "non-finite shapelet parameter");
-  int max_nmax = 0;
-  std::vector<int32_t> nmax(S);
-  std::vector<int64_t> coff(S);
-  int64_t ncoef = 0;
-  for (int s = 0; s < S; ++s) {
+    if (Sd > 0 && !finite_all(p, Sd)) return set_error(VP_EINVAL, "non-finite shapelet parameter");
+  // Shapelet components: one per spectral term of each shapelet (same
+  // position and frame; term q's flux carries ln(nu / nu_ref)^q).
+  std::vector<int> src;            // shapelet of the description
+  std::vector<int32_t> lp;         // its spectral term
+  std::vector<const double *> cp;  // its coefficients, packed for order d->s_nmax
+  for (int s = 0; s < Sd; ++s) {
     const int N = d->s_nmax[s];
     if (N < 0 || N > VP_NMAX_LIMIT) return set_error(VP_EINVAL, "shapelet %d: nmax %d outside 0..%d", s, N, VP_NMAX_LIMIT);
     if (!(d->s_beta1[s] > 0) || !(d->s_beta2[s] > 0)) return set_error(VP_EINVAL, "shapelet %d: beta must be positive", s);
     if (d->s_coeff_off[s] < 0) return set_error(VP_EINVAL, "shapelet %d: negative coefficient offset", s);
+    const int Q = d->s_nterm ? d->s_nterm[s] : 1;
+    if (Q < 1 || Q > VP_NTERM_LIMIT)
+      return set_error(VP_EINVAL, "shapelet %d: %d spectral terms outside 1..%d", s, Q, VP_NTERM_LIMIT);
     const int64_t cnt = (int64_t)(N + 1) * (N + 2) / 2;
-    const double *c = d->coeffs + d->s_coeff_off[s];
-    if (!finite_all(c, cnt)) return set_error(VP_EINVAL, "shapelet %d: non-finite coefficient", s);
+    for (int q = 0; q < Q; ++q) {
+      const double *c = d->coeffs + d->s_coeff_off[s] + q * cnt;
+      if (!finite_all(c, cnt)) return set_error(VP_EINVAL, "shapelet %d: non-finite coefficient", s);
+      src.push_back(s);
+      lp.push_back(q);
+      cp.push_back(c);
+    }
+  }
+  const int S = (int)src.size();
+  if ((int64_t)P + G + S > (1 << 28)) return set_error(VP_EINVAL, "too many components");
+  int max_nmax = 0;
+  std::vector<int32_t> nmax(S);
+  std::vector<int64_t> coff(S);
+  int64_t ncoef = 0;
+  for (int i = 0; i < S; ++i) {
+    const int N = d->s_nmax[src[i]];
+    const double *c = cp[i];
     // effective order: the highest n1 + n2 with a non-zero coefficient (orders
     // above it contribute nothing, and the kernels' work follows the order)
     int neff = 0;
-    for (int n1 = 0, i = 0; n1 <= N; ++n1)
-      for (int n2 = 0; n2 <= N - n1; ++n2, ++i)
-        if (c[i] != 0.0) neff = std::max(neff, n1 + n2);
-    nmax[s] = neff;
-    coff[s] = ncoef;
+    for (int n1 = 0, j = 0; n1 <= N; ++n1)
+      for (int n2 = 0; n2 <= N - n1; ++n2, ++j)
+        if (c[j] != 0.0) neff = std::max(neff, n1 + n2);
+    nmax[i] = neff;
+    coff[i] = ncoef;
     ncoef += (int64_t)(neff + 1) * (neff + 2) / 2;
     max_nmax = std::max(max_nmax, neff);
   }
@@ -512,14 +533,18 @@ int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *d, vp_sky **out) {
   k->max_nmax = max_nmax;
   k->h_nmax = nmax;
   const int J = P + G + S;
-  std::vector<double> ra(J), dec(J), sref(J), alpha(J), coeffs(ncoef);
+  std::vector<double> ra(J), dec(J), sref(J), alpha(J), coeffs(ncoef), b1(S), b2(S), spa(S);
   for (int i = 0; i < P; ++i) { ra[i] = d->p_ra[i]; dec[i] = d->p_dec[i]; sref[i] = d->p_sref[i]; alpha[i] = d->p_alpha[i]; }
   for (int i = 0; i < G; ++i) { ra[P + i] = d->g_ra[i]; dec[P + i] = d->g_dec[i]; sref[P + i] = d->g_sref[i]; alpha[P + i] = d->g_alpha[i]; }
+  bool terms = false;
   for (int i = 0; i < S; ++i) {
-    ra[P + G + i] = d->s_ra[i]; dec[P + G + i] = d->s_dec[i]; sref[P + G + i] = d->s_sref[i]; alpha[P + G + i] = d->s_alpha[i];
+    const int s = src[i];
+    ra[P + G + i] = d->s_ra[s]; dec[P + G + i] = d->s_dec[s]; sref[P + G + i] = d->s_sref[s]; alpha[P + G + i] = d->s_alpha[s];
+    b1[i] = d->s_beta1[s]; b2[i] = d->s_beta2[s]; spa[i] = d->s_pa[s];
+    terms = terms || lp[i] > 0;
     // packed n1-major over n1 + n2 <= nmax, re-packed for the effective order
-    const int N = d->s_nmax[i], M = nmax[i];
-    const double *c = d->coeffs + d->s_coeff_off[i];
+    const int N = d->s_nmax[s], M = nmax[i];
+    const double *c = cp[i];
     double *o = coeffs.data() + coff[i];
     for (int n1 = 0; n1 <= M; ++n1)
       for (int n2 = 0; n2 <= M - n1; ++n2)
@@ -549,9 +574,10 @@ int vp_create_sky(vp_ctx *ctx, const vp_sky_desc *d, vp_sky **out) {
   if (e == hipSuccess) e = upload(&k->g_maj, d->g_maj, G, k->mem);
   if (e == hipSuccess) e = upload(&k->g_min, d->g_min, G, k->mem);
   if (e == hipSuccess) e = upload(&k->g_pa, d->g_pa, G, k->mem);
-  if (e == hipSuccess) e = upload(&k->s_beta1, d->s_beta1, S, k->mem);
-  if (e == hipSuccess) e = upload(&k->s_beta2, d->s_beta2, S, k->mem);
-  if (e == hipSuccess) e = upload(&k->s_pa, d->s_pa, S, k->mem);
+  if (e == hipSuccess) e = upload(&k->s_beta1, b1.data(), S, k->mem);
+  if (e == hipSuccess) e = upload(&k->s_beta2, b2.data(), S, k->mem);
+  if (e == hipSuccess) e = upload(&k->s_pa, spa.data(), S, k->mem);
+  if (e == hipSuccess && terms) e = upload(&k->lpow, lp.data(), S, k->mem);
   if (e == hipSuccess) e = upload(&d_nmax, nmax.data(), S, k->mem);
   if (e == hipSuccess) e = upload(&d_coff, coff.data(), S, k->mem);
   if (e == hipSuccess) e = upload(&d_coeffs, coeffs.data(), ncoef, k->mem);

@@ -80,6 +80,8 @@ struct FluxArgs {
   double nu_ref;
   double ra0, dec0;
   double beam_fwhm, beam_nu_ref;
+  int j0;                      // first shapelet component
+  const int32_t *lpow;         // [J - j0] power q of ln(nu / nu_ref) multiplying a shapelet's flux, or null
   Derived d;
 };
 

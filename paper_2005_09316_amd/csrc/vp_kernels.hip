@@ -155,6 +155,11 @@ __device__ __forceinline__ void flux_one(const FluxArgs &a, int64_t idx) {
   if (k < a.K) {
     const double nu = a.freq[k];
     S = a.sref[j] * pow(nu / a.nu_ref, a.alpha[j]);
+    if (a.lpow && j >= a.j0) {
+      // spectral term q of a shapelet's coefficients: ln(nu / nu_ref)^q
+      const double x = log(nu / a.nu_ref);
+      for (int q = a.lpow[j - a.j0]; q > 0; --q) S *= x;
+    }
     if (a.beam_fwhm > 0.0) {
       // distance from the phase centre: sin(rho) = sqrt(l^2 + m^2)
       const double dec = a.dec[j], da = a.ra[j] - a.ra0;

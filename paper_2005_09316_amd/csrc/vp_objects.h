@@ -127,6 +127,7 @@ struct vp_sky {
   double *ra = nullptr, *dec = nullptr, *sref = nullptr, *alpha = nullptr;  // device [J]
   double *g_maj = nullptr, *g_min = nullptr, *g_pa = nullptr;               // device [G]
   double *s_beta1 = nullptr, *s_beta2 = nullptr, *s_pa = nullptr;          // device [S]
+  int32_t *lpow = nullptr;  // device [S]: spectral term of each shapelet component, or null (all 0)
   vp::ShpTiles tiles;
   int jobs = 0;
   vp::DeviceMem mem;

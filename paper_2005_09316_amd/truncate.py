@@ -47,10 +47,17 @@ def _orders(nmax: int):
     return n1, n2
 
 
+def _single_term(sky):
+    nterm = getattr(sky, "s_nterm", None)
+    if nterm is not None and np.any(np.asarray(nterm) != 1):
+        raise ValueError("truncation of shapelets with spectral terms is not defined")
+
+
 def component_flux(sky):
     """|I_j| of every point, Gaussian and shapelet basis function (at the
     reference frequency), and a matching list of (kind, component, packed
     coefficient index) with kind 0 = point, 1 = Gaussian, 2 = shapelet."""
+    _single_term(sky)
     flux = [np.abs(np.asarray(sky.p_sref, float)), np.abs(np.asarray(sky.g_sref, float))]
     kind = [np.zeros(len(sky.p_sref), int), np.ones(len(sky.g_sref), int)]
     comp = [np.arange(len(sky.p_sref)), np.arange(len(sky.g_sref))]
@@ -138,6 +145,7 @@ def truncate_by_flux(sky, f: float):
 
 def truncate_by_order(sky, nmax: int):
     """Set every shapelet coefficient with n1 + n2 > nmax to zero."""
+    _single_term(sky)
     coeffs = _shapelet_coeffs(sky)
     for s, c in enumerate(coeffs):
         n1, n2 = _orders(int(sky.s_nmax[s]))

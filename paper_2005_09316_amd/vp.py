@@ -28,6 +28,7 @@ VP_PREC_LUT = 6
 VP_C128, VP_C64 = 0, 1
 VP_JOB_PREDICT, VP_JOB_SUBTRACT = 0, 1
 VP_NMAX_LIMIT = 96
+VP_NTERM_LIMIT = 8
 VP_PEEL_MAX_ANT, VP_PEEL_MAX_ITER, VP_PEEL_MAX_CG = 256, 1000, 200
 
 PRECISIONS = {"fp64": VP_PREC_FP64, "mixed": VP_PREC_MIXED, "mixed_bf16": VP_PREC_MIXED_BF16,
@@ -63,7 +64,7 @@ class vp_sky_desc(ctypes.Structure):
                 ("g_maj", _dp), ("g_min", _dp), ("g_pa", _dp),
                 ("n_shp", ctypes.c_int32), ("s_ra", _dp), ("s_dec", _dp), ("s_sref", _dp), ("s_alpha", _dp),
                 ("s_beta1", _dp), ("s_beta2", _dp), ("s_pa", _dp),
-                ("s_nmax", _i32p), ("s_coeff_off", _i64p), ("coeffs", _dp)]
+                ("s_nmax", _i32p), ("s_coeff_off", _i64p), ("coeffs", _dp), ("s_nterm", _i32p)]
 
 
 class vp_job(ctypes.Structure):
@@ -186,7 +187,12 @@ def vp_create_sky(ctx: int, sky) -> int:
                     f("g_maj"), f("g_min"), f("g_pa"),
                     int(np.size(sky.s_ra)), f("s_ra"), f("s_dec"), f("s_sref"), f("s_alpha"),
                     f("s_beta1"), f("s_beta2"), f("s_pa"),
-                    _p(nmax, _i32p), _p(off, _i64p), f("coeffs"))
+                    _p(nmax, _i32p), _p(off, _i64p), f("coeffs"), None)
+    nterm = getattr(sky, "s_nterm", None)
+    if nterm is not None:
+        nt = np.ascontiguousarray(np.asarray(nterm, np.int32))
+        keep.append(nt)
+        d.s_nterm = _p(nt, _i32p)
     out = ctypes.c_void_p()
     _check(load().vp_create_sky(ctx, ctypes.byref(d), ctypes.byref(out)))
     return out.value

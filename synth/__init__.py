@@ -97,6 +97,9 @@ class Sky:
     s_coeff_off: np.ndarray  # int64
     coeffs: np.ndarray  # float64, packed per shapelet
     dc_redraws: int = 0
+    # None, or int32 [n_shp] spectral terms per shapelet: coefficient blocks
+    # C_0 .. C_{Q-1} following each other, C(nu) = sum_q C_q ln(nu/nu_ref)^q
+    s_nterm: Optional[np.ndarray] = None
 
     @property
     def n_point(self) -> int:
@@ -125,13 +128,22 @@ def empty_sky(nu_ref_hz: float = NU_REF_HZ) -> Sky:
                np.zeros(0, np.int32), np.zeros(0, np.int64), z)
 
 
+def shapelet_terms(sky: Sky) -> np.ndarray:
+    """Spectral terms per shapelet (1 each when the sky has none)."""
+    if sky.s_nterm is None:
+        return np.ones(sky.n_shp, np.int32)
+    return np.asarray(sky.s_nterm, np.int32)
+
+
 def concat_skies(*skies: Sky) -> Sky:
     """Component-wise concatenation (order preserved)."""
     out = {}
     for f in dataclasses.fields(Sky):
-        if f.name in ("nu_ref_hz", "dc_redraws", "s_coeff_off", "coeffs"):
+        if f.name in ("nu_ref_hz", "dc_redraws", "s_coeff_off", "coeffs", "s_nterm"):
             continue
         out[f.name] = np.concatenate([getattr(s, f.name) for s in skies])
+    if any(s.s_nterm is not None for s in skies):
+        out["s_nterm"] = np.concatenate([shapelet_terms(s) for s in skies]).astype(np.int32)
     coeffs, offs, base = [], [], 0
     for s in skies:
         coeffs.append(s.coeffs)
@@ -146,10 +158,11 @@ def select_components(sky: Sky, points=None, gauss=None, shapelets=None) -> Sky:
     def idx(sel, n):
         return np.arange(n) if sel is None else np.asarray(sel, dtype=np.int64)
     pi, gi, si = idx(points, sky.n_point), idx(gauss, sky.n_gauss), idx(shapelets, sky.n_shp)
+    terms = shapelet_terms(sky)
     coeffs, offs, base = [], [], 0
     for s in si:
         n = int(sky.s_nmax[s])
-        cnt = (n + 2) * (n + 1) // 2
+        cnt = (n + 2) * (n + 1) // 2 * int(terms[s])
         o = int(sky.s_coeff_off[s])
         coeffs.append(sky.coeffs[o:o + cnt])
         offs.append(base)
@@ -164,7 +177,30 @@ def select_components(sky: Sky, points=None, gauss=None, shapelets=None) -> Sky:
         s_nmax=sky.s_nmax[si].astype(np.int32),
         s_coeff_off=np.asarray(offs, np.int64),
         coeffs=np.concatenate(coeffs) if coeffs else np.zeros(0, np.float64),
+        s_nterm=None if sky.s_nterm is None else terms[si].astype(np.int32),
     )
+
+
+def with_spectral_terms(sky: Sky, rng: np.random.Generator, n_terms: int, scale: float = 0.3) -> Sky:
+    """The sky with every shapelet given n_terms spectral terms: C_0 is the
+    shapelet's coefficient set and C_q = (scale / q!) d_q * C_0 with d_q
+    drawn N(0, 1) per coefficient -- a spectral index that varies across the
+    source by about `scale` (ln(nu/nu_ref) is ~0.1 over a 30 MHz band at
+    165 MHz)."""
+    coeffs, offs, base = [], [], 0
+    for s in range(sky.n_shp):
+        n = int(sky.s_nmax[s])
+        cnt = (n + 2) * (n + 1) // 2
+        o = int(sky.s_coeff_off[s])
+        c0 = np.asarray(sky.coeffs[o:o + cnt], np.float64)
+        offs.append(base)
+        coeffs.append(c0)
+        for q in range(1, n_terms):
+            coeffs.append(scale / math.factorial(q) * rng.standard_normal(cnt) * c0)
+        base += cnt * n_terms
+    return dataclasses.replace(sky, s_coeff_off=np.asarray(offs, np.int64),
+                               coeffs=np.concatenate(coeffs) if coeffs else np.zeros(0, np.float64),
+                               s_nterm=np.full(sky.n_shp, n_terms, np.int32))
 
 
 # --------------------------------------------------------------------------

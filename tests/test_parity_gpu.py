@@ -252,3 +252,35 @@ def test_lookup_table_variant_within_interpolation_bound(ctx):
     assert np.all(np.isfinite(got))
     assert err <= bound
     assert err64 <= TOL[vp.VP_PREC_FP64]
+
+
+@pytest.mark.parametrize("prec,dtype", [(vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C128),
+                                        (vp.VP_PREC_MIXED, vp.VP_C64)])
+def test_spectral_terms_match_oracle(ctx, prec, dtype):
+    """Shapelets whose coefficients vary with frequency, C(nu) = sum_q C_q
+    ln(nu/nu_ref)^q (3 terms), over a 150-200 MHz band so that ln(nu/nu_ref)
+    reaches +-0.15; same bars as the plain model (error relative to the
+    channel's total flux, with xi(0) taken at that channel)."""
+    import dataclasses
+    obs, sky = synth.make_config(2, n_tiles=16, n_time=2, n_chan=5, shapelet_nmax=[40, 33])
+    obs = dataclasses.replace(obs, freq_hz=np.linspace(150e6, 200e6, 5))
+    multi = synth.with_spectral_terms(sky, np.random.default_rng(21), 3, scale=0.5)
+    ref = oracle.predict(obs, multi)
+    _log("spectral terms: prec", prec, "dtype", dtype)
+    with Handles(ctx, obs, multi) as h:
+        got = run(ctx, h.obs, h.sky, obs, prec, dtype)
+    err = oracle.error_metric(got, ref, obs, multi)
+    _log("  error / total flux = %.3e" % err)
+    tol = TOL[prec] if dtype == vp.VP_C128 else max(TOL[prec], 1e-6)
+    assert np.all(np.isfinite(got))
+    assert err <= tol
+
+
+def test_spectral_terms_rejected_outside_limits(ctx):
+    obs, sky = synth.make_config(0, n_tiles=6, n_chan=2, shapelet_nmax=[4])
+    import dataclasses
+    for q in (0, vp.VP_NTERM_LIMIT + 1):
+        bad = dataclasses.replace(sky, s_nterm=np.array([q], np.int32),
+                                  coeffs=np.tile(sky.coeffs, max(q, 1)))
+        with pytest.raises(vp.VPError):
+            vp.vp_create_sky(ctx, bad)

@@ -69,3 +69,12 @@ def test_truncate_by_order_zeroes_high_orders():
     c = t.coeffs[:n1.size]
     assert np.all(c[n1 + n2 > 4] == 0.0)
     assert np.array_equal(c[n1 + n2 <= 4], sky.coeffs[:n1.size][n1 + n2 <= 4])
+
+
+def test_spectral_term_skies_are_refused():
+    _, sky = synth.make_config(0, n_tiles=8, n_chan=2, shapelet_nmax=[6])
+    multi = synth.with_spectral_terms(sky, np.random.default_rng(1), 2)
+    with pytest.raises(ValueError):
+        truncate.truncate_by_flux(multi, 0.9)
+    with pytest.raises(ValueError):
+        truncate.truncate_by_order(multi, 3)
