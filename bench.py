@@ -52,17 +52,21 @@ if ROOT not in sys.path:
 
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic VALU issue slots per evaluation (transcendentals issue at half rate):
-#   point:    phase scale 1 + reduction 1 + convert 1 + sin 2 + cos 2 + complex MAC 2 = 9
-#   Gaussian: point + exponent scale 1 + exp2 2 + flux x envelope 1              = 13
+# Algorithmic VALU issue slots per evaluation (transcendentals issue at half rate).
+# With uniformly spaced channels (this workload) the mixed kernel evaluates the
+# phasor of 3 channels of each 8 and the channel step, and rotates the others:
+#   per 8 channels: 4 x (phase scale 1 + reduction 1 + convert 1 + sin 2 + cos 2)
+#                   + 5 complex rotations x 4 + 8 complex MACs x 2 = 64
+#   point:    64 / 8                                                       = 8
+#   Gaussian: point + exponent scale 1 + exp2 2 + flux x envelope 1        = 12
 #   per (row, component): u l + v m + w (n - 1), 3 FMAs shared by the row's channels
-SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 9, 13, 3
+SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 8, 12, 3
 
 # HBM bytes per launch of the point/Gaussian kernel on this workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (summary in
 # profiles/k_pg_tile_mwa-like_hbm-traffic.md), valid for the kernel source
 # whose hash is recorded; reported as null once that source changes.
-PG_TRAFFIC = {"bytes": 148.1e6 + 29.1e6, "source_sha256_16": "9a001eb5db053faa"}
+PG_TRAFFIC = {"bytes": 114.9e6 + 29.1e6, "source_sha256_16": "434bbe69ea45503e"}
 
 
 # dense MFMA peaks and the FP64 vector peak (TFLOP/s)
@@ -559,7 +563,7 @@ def main():
     slots = (pg_evals_pt * SLOTS_POINT + pg_evals_g * SLOTS_GAUSS
              + nrows * (sky.n_point + sky.n_gauss) * SLOTS_ROW_COMP)
     achieved = slots / (pg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_pg_tile<mixed>", "achieved": round(achieved, 3),
+    roofline = {"bound": "alu", "kernel": "k_pg_tile<mixed, uniform channels>", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s (VALU issue slots)",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": PG_TRAFFIC["bytes"] if _pg_source_hash() == PG_TRAFFIC["source_sha256_16"] else None,

@@ -302,6 +302,8 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.n_rb = (int)((a.nrows + kTileRows - 1) / kTileRows);
   a.n_cb = obs->Kpad / kPgChan;
   a.lut = lut;
+  a.dfk = obs->dfk;
+  a.uniform = obs->uniform;
   hipError_t e;
   {
     ProfScope ps(ctx, stream, 1);
@@ -429,6 +431,16 @@ int vp_create_obs(vp_ctx *ctx, const vp_obs_desc *desc, vp_obs **out) {
   o->h_freq.assign(desc->freq_hz, desc->freq_hz + desc->n_chan);
   std::vector<double> fk(o->Kpad);
   for (int k = 0; k < o->Kpad; ++k) fk[k] = desc->freq_hz[std::min(k, o->K - 1)] / kLightSpeed;
+  if (o->K >= 2) {
+    // uniformly spaced channels let the mixed path rotate phasors between
+    // channels; the grid must hold to 1e-12 of nu/c (phase error below
+    // 1e-8 turns for |t0| up to 1e4 m)
+    const double d = (fk[o->K - 1] - fk[0]) / (o->K - 1);
+    bool uni = d != 0.0;
+    for (int k = 0; k < o->K && uni; ++k) uni = std::fabs(fk[k] - std::fma((double)k, d, fk[0])) <= 1e-12 * std::fabs(fk[0]);
+    o->uniform = uni ? 1 : 0;
+    o->dfk = uni ? d : 0.0;
+  }
   hipError_t e = upload(&o->uvw, desc->uvw_m, 3 * nrows, o->mem);
   if (e == hipSuccess) e = upload(&o->freq, desc->freq_hz, (int64_t)o->K, o->mem);
   if (e == hipSuccess) e = upload(&o->fk, fk.data(), (int64_t)o->Kpad, o->mem);

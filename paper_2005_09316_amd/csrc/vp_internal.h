@@ -115,6 +115,8 @@ struct TileArgs {
   int conj;            // 1 when the exponent sign is -1
   int nb;              // FP64 shapelet kernel: order bucket
   const float *lut;    // basis table of the lookup-table variant, or null
+  double dfk;          // (nu_{k+1} - nu_k) / c when the channels are uniformly spaced
+  int uniform;         // 1: channels uniformly spaced (the mixed path rotates phasors by dfk)
 };
 
 // ---------------------------------------------------------------------------

@@ -293,9 +293,15 @@ struct PgSmem {
 };
 
 // One tile: kTileRows rows x kPgChan channels starting at channel block cb.
-template <int PREC>
+// UNI (mixed path, uniformly spaced channels): the phasors of channels 0, 3
+// and 6 of the tile are evaluated (FP64 phase, FP32 sincos) and the others
+// are those rotated by one channel step, e^{+-2 pi i t0 dnu/c}: 4 sincos and
+// 5 complex rotations per (row, component) instead of 8 sincos, with at most
+// one rotation between a channel and an evaluated phasor.
+template <int PREC, bool UNI = false>
 __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
                                         PgSmem<typename PgTypes<PREC>::acc_t> &sm) {
+  static_assert(!UNI || (PREC == kMixed && kPgChan == 8), "channel rotation is a mixed-path, 8-channel scheme");
   typedef typename PgTypes<PREC>::acc_t acc_t;
   constexpr int KB = kPgChan;
   double4 *s_pos = sm.pos;
@@ -325,6 +331,9 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
     f2[k] = (float)(f[k] * f[k]);
   }
   const acc_t uu = (acc_t)(u * u), vv = (acc_t)(v * v), uv = (acc_t)(u * v);
+  // anchors of the rotation scheme: nu/c of tile channels 3 and 6 on the
+  // uniform grid (also when they lie past the last channel)
+  const double fa3 = fma(3.0, a.dfk, f[0]), fa6 = fma(6.0, a.dfk, f[0]);
 
   const int J0[2] = {0, a.P};
   const int JN[2] = {a.P, a.P + a.G};
@@ -377,6 +386,31 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
             if (kind == 1) S *= __builtin_amdgcn_exp2f(-(float)Q * f2[k]);
             prt_re[k] = fmaf(S, c, (float)prt_re[k]);
             prt_im[k] = fmaf(S, s, (float)prt_im[k]);
+          }
+        } else if (UNI) {
+          const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
+          float c[KB], s[KB], cd, sd;
+          turns_sincos_mixed(t0 * f[0], c[0], s[0]);
+          turns_sincos_mixed(t0 * fa3, c[3], s[3]);
+          turns_sincos_mixed(t0 * fa6, c[6], s[6]);
+          turns_sincos_mixed(t0 * a.dfk, cd, sd);
+          // one step up from channels 0, 3, 6; one step down from 3, 6
+          c[1] = fmaf(c[0], cd, -s[0] * sd);
+          s[1] = fmaf(s[0], cd, c[0] * sd);
+          c[4] = fmaf(c[3], cd, -s[3] * sd);
+          s[4] = fmaf(s[3], cd, c[3] * sd);
+          c[7] = fmaf(c[6], cd, -s[6] * sd);
+          s[7] = fmaf(s[6], cd, c[6] * sd);
+          c[2] = fmaf(c[3], cd, s[3] * sd);
+          s[2] = fmaf(s[3], cd, -c[3] * sd);
+          c[5] = fmaf(c[6], cd, s[6] * sd);
+          s[5] = fmaf(s[6], cd, -c[6] * sd);
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            float S = (float)s_flux[jj][k];
+            if (kind == 1) S *= __builtin_amdgcn_exp2f(-(float)Q * f2[k]);
+            prt_re[k] = fmaf(S, c[k], (float)prt_re[k]);
+            prt_im[k] = fmaf(S, s[k], (float)prt_im[k]);
           }
         } else {
           const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
@@ -432,11 +466,11 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
   }
 }
 
-template <int PREC>
+template <int PREC, bool UNI = false>
 __global__ __launch_bounds__(kTileRows) void k_pg_tile(TileArgs a) {
   __shared__ PgSmem<typename PgTypes<PREC>::acc_t> sm;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  pg_tile<PREC>(a, tile % a.n_rb, tile / a.n_rb, sm);
+  pg_tile<PREC, UNI>(a, tile % a.n_rb, tile / a.n_rb, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,7 +1219,10 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
     if (tid == 0 && tile == 0)
       __hip_atomic_store(&H->started[slot], job.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     const int rb = (int)(tile % job.a.n_rb), cb = (int)(tile / job.a.n_rb);
-    pg_tile<kMixed>(job.a, rb, cb, sm.pg);
+    if (job.a.uniform)
+      pg_tile<kMixed, true>(job.a, rb, cb, sm.pg);
+    else
+      pg_tile<kMixed>(job.a, rb, cb, sm.pg);
     __syncthreads();  // the tile's point/Gaussian sums are visible to the whole workgroup
     if (job.a.S > 0) {
       shp_tile<double, double, kCmBf16x3>(job.a, rb, 2 * cb, sm.shp);
@@ -1266,7 +1303,10 @@ hipError_t launch_pg(const TileArgs &a, int prec, hipStream_t s) {
       hipLaunchKernelGGL(k_pg_tile<kFP32>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL(k_pg_tile<kMixed>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+      if (a.uniform)
+        hipLaunchKernelGGL((k_pg_tile<kMixed, true>), dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_pg_tile<kMixed, false>), dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
       break;
   }
   return hipGetLastError();

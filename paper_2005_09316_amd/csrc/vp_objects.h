@@ -112,6 +112,8 @@ struct vp_obs {
   double *uvw = nullptr;  // device [T*B][3]
   double *freq = nullptr; // device [K]
   double *fk = nullptr;   // device [Kpad], nu/c
+  double dfk = 0;         // channel step of nu/c when uniform
+  int uniform = 0;        // channels uniformly spaced (to 1e-12 of nu/c)
   std::vector<double> h_freq;
   int jobs = 0;           // pending serving jobs using it (guarded by ctx->mu)
   vp::DeviceMem mem;

@@ -162,6 +162,8 @@ static int admit(Scheduler *s, JobRec *j) {
   a.conj = obs->sign < 0;
   a.n_rb = (int)((a.nrows + kTileRows - 1) / kTileRows);
   a.n_cb = obs->Kpad / kPgChan;
+  a.dfk = obs->dfk;
+  a.uniform = obs->uniform;
   const int slot = s->free_slots.back();
   s->free_slots.pop_back();
   j->slot = slot;

@@ -41,13 +41,20 @@ def _case(name):
                                  shapelet_nmax=[54, 33])
     if name == "fornax-mid":
         return synth.make_config(2, n_tiles=20, n_time=2, n_chan=6)
+    if name == "mwa-nonuniform":
+        # channels at irregular frequencies: the mixed path evaluates every
+        # channel's phasor (no rotation between channels)
+        rng = np.random.default_rng(31)
+        freqs = np.sort(rng.uniform(170e6, 190e6, 11))
+        return synth.make_config(1, n_tiles=20, n_time=2, n_chan=11, n_point=200, n_gauss=40,
+                                 shapelet_nmax=[20], freq_hz=freqs)
     if name == "nmax-limit":
         return synth.make_config(0, n_tiles=16, n_time=2, n_chan=5, n_point=3, n_gauss=2,
                                  shapelet_nmax=[96, 0, 1, 31, 32, 63, 64])
     raise KeyError(name)
 
 
-CASES = ["tiny", "mwa-mid", "fornax-mid", "nmax-limit"]
+CASES = ["tiny", "mwa-mid", "fornax-mid", "mwa-nonuniform", "nmax-limit"]
 _REF = {}
 
 
