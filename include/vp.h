@@ -62,7 +62,8 @@ extern "C" {
 
 /* precision paths */
 #define VP_PREC_FP64 0        /* FP64 everywhere (phase, sincos, envelopes, recurrence, contraction, sums) */
-#define VP_PREC_MIXED 1       /* FP64 phase + range reduction; FP32 sincos/envelopes/Kahan sums;
+#define VP_PREC_MIXED 1       /* FP64 phase + range reduction; FP32 sincos/envelopes, FP32 partial
+                                 sums of 8 terms added into FP64;
                                  FP64 Hermite recurrence; shapelet contraction on MFMA with the
                                  coefficients and Hermite values split into 3 BF16 parts (6 products,
                                  FP32 accumulation, folded into FP64 per 32 orders) */

@@ -12,19 +12,23 @@
 //               (row, component) is t0 = u l + v m + w (n-1) in metres (FP64);
 //               per channel t = t0 nu/c, reduced to a fraction of a turn in
 //               FP64, then sin/cos of 2 pi t in FP32 on the transcendental
-//               unit (input in turns).  Sums are plain FP32 over kFlush
-//               components, then Kahan-compensated across those partial sums.
+//               unit (input in turns); with uniformly spaced channels the
+//               mixed path evaluates 3 of every 8 channels and the channel
+//               step and rotates the other phasors.  Sums are plain FP32
+//               over kFlush components, then added into FP64 sums (the
+//               FP32-only path: Kahan-compensated FP32 sums).
 //   k_shp_mfma  shapelets.  Per (visibility, shapelet): rotate uvw into the
-//               shapelet's frame, run the normalised Hermite recurrence for
+//               shapelet's frame, walk the rescaled Hermite recurrence for
 //               both axes (FP64: it costs the same issue slots as FP32 on this
 //               chip and removes the argument-rounding and underflow error of
 //               an FP32 recurrence), contract against the signed coefficient
-//               matrix on MFMA (v_mfma_f32_32x32x2f32: n1 on M, n2 on K,
-//               32 visibilities on N, n2 split by parity into real/imaginary
-//               accumulators, 32-row blocks beyond the n1 + n2 <= N triangle
-//               skipped), finish the n1 sum against the first axis in the
-//               MFMA output layout, and add flux x envelope x phase into a
-//               Kahan accumulator held in LDS.
+//               matrix on MFMA (n1 on M, n2 on K split by parity into
+//               real/imaginary accumulators, 32 visibilities on N; 32 x 32
+//               blocks that meet the n1 + n2 <= N triangle only;
+//               v_mfma_f32_32x32x16_bf16 on 3-way BF16 splits, or
+//               v_mfma_f32_32x32x2_f32), fold the n1 sum against the first
+//               axis in FP64 in the MFMA output layout, and add flux x
+//               envelope x phase into an FP64 accumulator held in LDS.
 //   k_shp_fp64  the FP64 path of the shapelet term on the vector ALU (and
 //               the lookup-table variant of the basis).
 //
@@ -318,9 +322,17 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
 #pragma unroll
   for (int k = 0; k < KB; ++k) f[k] = a.fk[k0 + k];
 
+  // Partial sums over kFlush components in acc_t; across them, the mixed
+  // path adds the partials into FP64 sums (FP64 adds issue at the FP32 rate
+  // here, and two operations per value replace Kahan's four), the FP32-only
+  // path keeps Kahan-compensated FP32 sums, the FP64 path plain FP64 sums.
   acc_t sum_re[KB], sum_im[KB], cmp_re[KB], cmp_im[KB], prt_re[KB], prt_im[KB];
+  double dsum_re[KB], dsum_im[KB];
 #pragma unroll
-  for (int k = 0; k < KB; ++k) sum_re[k] = sum_im[k] = cmp_re[k] = cmp_im[k] = prt_re[k] = prt_im[k] = 0;
+  for (int k = 0; k < KB; ++k) {
+    sum_re[k] = sum_im[k] = cmp_re[k] = cmp_im[k] = prt_re[k] = prt_im[k] = 0;
+    dsum_re[k] = dsum_im[k] = 0.0;
+  }
 
   // FP32-path copies of the row's coordinates
   const float uf = (float)u, vf = (float)v, wf = (float)w;
@@ -427,8 +439,13 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
         if ((jj & (kFlush - 1)) == kFlush - 1 || jj == n - 1) {
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
-            kahan_add(sum_re[k], cmp_re[k], prt_re[k]);
-            kahan_add(sum_im[k], cmp_im[k], prt_im[k]);
+            if constexpr (PREC == kMixed) {
+              dsum_re[k] += (double)prt_re[k];
+              dsum_im[k] += (double)prt_im[k];
+            } else {
+              kahan_add(sum_re[k], cmp_re[k], prt_re[k]);
+              kahan_add(sum_im[k], cmp_im[k], prt_im[k]);
+            }
             prt_re[k] = prt_im[k] = 0;
           }
         }
@@ -442,8 +459,10 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
   for (int k = 0; k < KB; ++k) {
     if (k0 + k >= a.K) break;
     const int64_t idx = base + k0 + k;
+    const double tre = PREC == kMixed ? dsum_re[k] : (double)sum_re[k] - (double)cmp_re[k];
+    const double tim = PREC == kMixed ? dsum_im[k] : (double)sum_im[k] - (double)cmp_im[k];
     if (a.c64) {
-      float re = (float)(sum_re[k] - cmp_re[k]), im = (float)(sum_im[k] - cmp_im[k]);
+      float re = (float)tre, im = (float)tim;
       if (a.conj) im = -im;
       float2 *o = (float2 *)a.vis + idx;
       if (a.subtract) {
@@ -453,7 +472,7 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
         *o = make_float2(re, im);
       }
     } else {
-      double re = (double)sum_re[k] - (double)cmp_re[k], im = (double)sum_im[k] - (double)cmp_im[k];
+      double re = tre, im = tim;
       if (a.conj) im = -im;
       double2 *o = (double2 *)a.vis + idx;
       if (a.subtract) {
