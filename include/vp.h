@@ -25,7 +25,9 @@
  *                 index per component (Sec. 4.1); B_j is 1 (flat beam, Sec. 3.1)
  *                 or an optional Gaussian power pattern about the phase centre,
  *                 exp(-4 ln2 rho_j^2 / Theta(nu)^2), Theta(nu) = Theta_ref nu_ref_beam / nu.
- *   - peel:       R = D - V, the residual of Sec. 5.1 with unit gains.
+ *   - peel:       R = D - V, the residual of Sec. 5.1 with unit gains
+ *                 (vp_subtract), or R = D - g_ant1 g_ant2^* V with per-tile gains
+ *                 fitted per (time, channel) as in Sec. 5.1 (vp_peel).
  *
  * Conventions: angles in radians, FWHMs and beta as FWHM in radians, PA east of
  * north, fluxes in Jy, frequencies in Hz.  n - 1 is formed as
