@@ -87,3 +87,39 @@ def test_peel_subtracts_the_gain_corrupted_model():
     gains, res = oracle.peel(data, model, a1, a2, n)
     assert gains.shape == (T, K, n)
     assert np.max(np.abs(res)) < 1e-10 * np.max(np.abs(data))
+
+
+def test_two_tiles_closed_form():
+    # one baseline: the data fix g_0 g_1^* = V / I exactly; from unit gains the
+    # minimum-norm steps keep the mean phase at zero, so g_1 = conj(g_0) up
+    # to amplitude: |g_0| = |g_1| = sqrt(|V / I|), arg g_0 = -arg g_1
+    a1, a2 = np.array([0], np.int32), np.array([1], np.int32)
+    m = np.array([2.0 - 1.0j])
+    v = np.array([(1.3 * np.exp(0.4j)) * m[0]])
+    g = oracle.calibrate_cell(v, m, a1, a2, 2, n_iter=30)
+    ratio = v[0] / m[0]
+    assert abs(g[0] * np.conj(g[1]) - ratio) < 1e-12
+    assert abs(abs(g[0]) - abs(g[1])) < 1e-12
+    assert abs(np.angle(g[0]) + np.angle(g[1])) < 1e-12
+
+
+try:
+    from hypothesis import given, settings, strategies as st
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    @settings(max_examples=25, deadline=None)
+    @given(n=st.integers(3, 9), seed=st.integers(0, 2 ** 31 - 1))
+    def test_noise_free_recovery_random_arrays(n, seed):
+        """Any connected array with all pairs, random model and gains within
+        the linear regime: the calibrated products g_i g_j^* reproduce the
+        true ones and the step gauge keeps the mean phase change at zero."""
+        rng = np.random.default_rng(seed)
+        a1, a2 = synth.antenna_pairs(n)
+        model = rng.lognormal(0.0, 0.3, a1.size) * np.exp(2j * np.pi * rng.random(a1.size))
+        g_true = synth.random_gains(rng, 1, 1, n, amp_sigma=0.1, phase_sigma=0.3)[0, 0]
+        v = g_true[a1] * np.conj(g_true[a2]) * model
+        g = oracle.calibrate_cell(v, model, a1, a2, n, n_iter=15)
+        prod = g[a1] * np.conj(g[a2])
+        assert np.max(np.abs(prod - g_true[a1] * np.conj(g_true[a2]))) < 1e-9
