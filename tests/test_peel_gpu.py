@@ -265,3 +265,40 @@ def test_peel_rejects_bad_arguments(ctx, bad):
     finally:
         vp.vp_destroy_sky(sh)
         vp.vp_destroy_obs(oh)
+
+
+def test_peel_paper_observation_chunked(ctx):
+    """The paper's peel observation (128 tiles, 15 x 8 s, 384 channels: 5760
+    cells, whose tables take three launches of at most 1 GiB) with its
+    p_max = 86 lobes under gains, mixed path, complex64: cells in the first
+    and last launch against the oracle."""
+    import torch
+    obs, _clean, lobes = synth.make_paper_cost_comparison()
+    n_ant, n_iter = int(obs.n_tiles), 5
+    a1, a2 = synth.antenna_pairs(n_ant)
+    cells = [(0, 3), (14, 383)]
+    rng = np.random.default_rng(515)
+    G = synth.random_gains(rng, obs.n_time, obs.n_chan, n_ant)
+    data = synth.noise_c64((obs.n_time, obs.n_bl, obs.n_chan), seed=516).astype(np.complex128)
+    models = {}
+    for (t, k) in cells:
+        sub = dataclasses.replace(obs, n_time=1, uvw_m=np.ascontiguousarray(obs.uvw_m[t:t + 1]), n_chan=1,
+                                  freq_hz=obs.freq_hz[k:k + 1])
+        M = oracle.predict(sub, lobes).reshape(-1)
+        models[(t, k)] = (sub, M)
+        data[t, :, k] += G[t, k, a1] * np.conj(G[t, k, a2]) * M
+    data = _input_as(data, vp.VP_C64)
+    _log("peel paper observation: %d cells, cells checked %s" % (obs.n_time * obs.n_chan, cells))
+    g, res = _run_peel(ctx, obs, lobes, a1, a2, n_ant, data, n_iter, vp.VP_PREC_MIXED, vp.VP_C64)
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(res))
+    for (t, k) in cells:
+        sub, M = models[(t, k)]
+        v = data[t, :, k]
+        g_ref = oracle.calibrate_cell(v, M, a1, a2, n_ant, n_iter)
+        r_ref = v - g_ref[a1] * np.conj(g_ref[a2]) * M
+        p, p_ref = g[t, k, a1] * np.conj(g[t, k, a2]), g_ref[a1] * np.conj(g_ref[a2])
+        ep = np.abs(p - p_ref).max() / np.abs(p_ref).max()
+        er = np.abs(res[t, :, k] - r_ref).max() / oracle.total_flux(sub, lobes)[0]
+        _log("  cell (%d, %d): g_i g_j^* %.3e, residual / F %.3e" % (t, k, ep, er))
+        assert ep <= GAIN_FACTOR * PRED_BAR[vp.VP_PREC_MIXED]
+        assert er <= RES_FACTOR * PRED_BAR[vp.VP_PREC_MIXED]
