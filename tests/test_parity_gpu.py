@@ -291,3 +291,44 @@ def test_spectral_terms_rejected_outside_limits(ctx):
                                   coeffs=np.tile(sky.coeffs, max(q, 1)))
         with pytest.raises(vp.VPError):
             vp.vp_create_sky(ctx, bad)
+
+
+def _random_case(seed):
+    """A small seeded configuration with irregular sizes: 2-40 tiles, 1-3
+    times, 1-13 channels (uniformly or irregularly spaced), 0-300 points,
+    0-40 Gaussians, 0-3 shapelets of order 0-96."""
+    import dataclasses
+    rng = np.random.default_rng(9000 + seed)
+    n_tiles = int(rng.integers(2, 41))
+    n_time = int(rng.integers(1, 4))
+    n_chan = int(rng.integers(1, 14))
+    if rng.random() < 0.5:
+        freqs = np.linspace(150e6, 200e6, n_chan) if n_chan > 1 else np.array([182e6])
+    else:
+        freqs = np.sort(rng.uniform(150e6, 200e6, n_chan))
+    nmax = [int(x) for x in rng.integers(0, 97, int(rng.integers(0, 4)))]
+    obs, sky = synth.make_config(1, seed=9100 + seed, n_tiles=n_tiles, n_time=n_time, n_chan=n_chan,
+                                 n_point=int(rng.integers(0, 301)), n_gauss=int(rng.integers(0, 41)),
+                                 shapelet_nmax=nmax, freq_hz=freqs)
+    if rng.random() < 0.3:
+        obs = dataclasses.replace(obs, beam_fwhm_rad=0.0, beam_nu_ref_hz=0.0)
+    return obs, sky
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configurations(ctx, seed):
+    obs, sky = _random_case(seed)
+    _log("random case %d: tiles %d, times %d, channels %d, points %d, Gaussians %d, shapelet orders %s"
+         % (seed, obs.n_tiles, obs.n_time, obs.n_chan, sky.n_point, sky.n_gauss, list(sky.s_nmax)))
+    ref = oracle.predict(obs, sky)
+    F = oracle.total_flux(obs, sky)
+    with Handles(ctx, obs, sky) as h:
+        for prec, dtype in ((vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C64)):
+            got = run(ctx, h.obs, h.sky, obs, prec, dtype)
+            assert np.all(np.isfinite(got))
+            if not np.any(F > 0):
+                assert np.max(np.abs(got)) == 0.0
+                continue
+            err = oracle.error_metric(got, ref, obs, sky)
+            _log("  precision %d: error / total flux %.3e" % (prec, err))
+            assert err <= (TOL[prec] if dtype == vp.VP_C128 else 1e-6)
