@@ -112,7 +112,8 @@ __global__ __launch_bounds__(256) void k_gain_prep(GainArgs a) {
   }
 }
 
-// Sums of two values over the workgroup in one pass.
+// Sums of two values over the workgroup (NT threads) in one pass.
+template <int NT>
 __device__ __forceinline__ double2 block_sum2(double u, double v, double2 *red) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -125,7 +126,7 @@ __device__ __forceinline__ double2 block_sum2(double u, double v, double2 *red) 
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int w = 0; w < kGainThreads / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     s.x += red[w].x;
     s.y += red[w].y;
   }
@@ -138,7 +139,7 @@ __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
   return i * n - i * (i - 1) / 2 + (j - i);
 }
 
-// One workgroup of kGainThreads threads per cell.  Thread (k, part) with
+// One workgroup of NT threads per cell.  Thread (k, part) with
 // k = tid mod nk (nk = n rounded up to 64) and part = tid / nk sums over
 // the part-th slice o0 <= o < o1 of the tiles (wave-uniform); the part-0
 // thread of tile k holds the tile's gain and its conjugate-gradient state.
@@ -146,21 +147,21 @@ __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
 // step uses these W values for its diagonal too, so that i g stays its
 // exact null vector; the right-hand side uses the FP64 tables.  The solve
 // is conjugate gradients preconditioned by that diagonal (Jacobi).
-template <typename WT>
-__global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
+template <typename WT, int NT>
+__global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
   double2 *y = g + kPeelMaxAnt;                   // [kPeelMaxAnt] g_o p_o^* of the current direction
-  double2 *pa = y + kPeelMaxAnt;                  // [kGainThreads] partial sums
-  double *pv = (double *)(pa + kGainThreads);     // [kPeelMaxAnt] projection scratch
+  double2 *pa = y + kPeelMaxAnt;                  // [NT] partial sums
+  double *pv = (double *)(pa + NT);               // [kPeelMaxAnt] projection scratch
   int *comp = (int *)(pv + kPeelMaxAnt);          // [kPeelMaxAnt] connected component of each tile
-  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [kGainThreads / 64] reduction scratch
-  WT *W = (WT *)(red + kGainThreads / 64);        // [n (n + 1) / 2] |I|^2, packed with the diagonal
+  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [NT / 64] reduction scratch
+  WT *W = (WT *)(red + NT / 64);                  // [n (n + 1) / 2] |I|^2, packed with the diagonal
 
   const int cl = blockIdx.x, cell = a.cell0 + cl;
   const int t = cell / a.K, kc = cell % a.K;
   const int n = a.n_ant, tid = threadIdx.x;
-  const int nk = (n + 63) & ~63, parts = kGainThreads / nk;
+  const int nk = (n + 63) & ~63, parts = NT / nk;
   const int k = tid % nk;
   const int pt = __builtin_amdgcn_readfirstlane(tid / nk);  // nk is a multiple of 64: one part per wave
   const int span = (n + parts - 1) / parts;
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
 
   const double2 *X = a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
   const double *Wf = a.wf + (int64_t)cl * n * n;  // |I|^2 [o n + k], FP64, zero for o == k
-  for (int idx = tid; idx < n * n; idx += kGainThreads) {
+  for (int idx = tid; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx - i * n;
     if (i <= j) W[packed_index(n, i, j)] = (WT)Wf[idx];
   }
@@ -258,9 +259,9 @@ __global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
     // below this |r|^2 the right-hand side is rounding noise: no step
     double2 x = make_double2(0.0, 0.0), res = r;
     double2 z = make_double2(minv * r.x, minv * r.y), pdir = z;
-    const double2 s0 = block_sum2(res.x * res.x + res.y * res.y, scale * scale, red);
+    const double2 s0 = block_sum2<NT>(res.x * res.x + res.y * res.y, scale * scale, red);
     const double floor2 = kGainFloor * kGainFloor * s0.y;
-    double rr = s0.x, rz = block_sum2(res.x * z.x + res.y * z.y, 0.0, red).x;
+    double rr = s0.x, rz = block_sum2<NT>(res.x * z.x + res.y * z.y, 0.0, red).x;
     const double rr0 = rr;
     for (int cg = 0; cg < a.max_cg; ++cg) {
       if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2) || !(rz > 0.0)) break;
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
         const double2 gs = cmul(gk, s);
         q = make_double2(Dt * pdir.x + gs.x, Dt * pdir.y + gs.y);
       }
-      const double pq = block_sum2(pdir.x * q.x + pdir.y * q.y, 0.0, red).x;
+      const double pq = block_sum2<NT>(pdir.x * q.x + pdir.y * q.y, 0.0, red).x;
       if (!(pq > 0.0)) break;
       const double alpha = rz / pq;
       x.x += alpha * pdir.x;
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
       res.x -= alpha * q.x;
       res.y -= alpha * q.y;
       z = make_double2(minv * res.x, minv * res.y);
-      const double2 s1 = block_sum2(res.x * res.x + res.y * res.y, res.x * z.x + res.y * z.y, red);
+      const double2 s1 = block_sum2<NT>(res.x * res.x + res.y * res.y, res.x * z.x + res.y * z.y, red);
       const double beta = s1.y / rz;
       pdir = make_double2(z.x + beta * pdir.x, z.y + beta * pdir.y);
       rr = s1.x;
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
   if (a.gains && own) a.gains[(int64_t)cell * n + k] = gk;
   if (a.subtract) {
     const int64_t base = (int64_t)t * a.B * a.K + kc;  // element (t, b, kc) at base + b K
-    for (int b = tid; b < a.B; b += kGainThreads) {
+    for (int b = tid; b < a.B; b += NT) {
       const int64_t i = base + (int64_t)b * a.K;
       const double2 m = load_vis(a.model, a.c64, i);
       const double2 v = load_vis(a.data, a.c64, i);
@@ -316,14 +317,24 @@ __global__ __launch_bounds__(kGainThreads) void k_gain_solve(GainArgs a) {
   }
 }
 
-size_t gain_smem_bytes(int n_ant, bool w64) {
+size_t gain_smem_bytes(int n_ant, bool w64, int threads) {
   const size_t packed = (size_t)n_ant * (n_ant + 1) / 2;
-  return kPeelMaxAnt * (2 * sizeof(double2) + sizeof(double) + sizeof(int)) + kGainThreads * sizeof(double2) +
-         (kGainThreads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
+  return kPeelMaxAnt * (2 * sizeof(double2) + sizeof(double) + sizeof(int)) + threads * sizeof(double2) +
+         (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
+}
+
+template <typename WT, int NT>
+static hipError_t launch_solve(const GainArgs &a, hipStream_t s) {
+  const size_t sm = gain_smem_bytes(a.n_ant, sizeof(WT) == sizeof(double), NT);
+  hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<WT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gain_solve<WT, NT>), dim3((unsigned)a.ncell), dim3(NT), sm, s, a);
+  return hipGetLastError();
 }
 
 bool gain_supported(int n_ant) {
-  return n_ant >= 2 && n_ant <= kPeelMaxAnt && gain_smem_bytes(n_ant, false) <= kPeelSmemMax;
+  return n_ant >= 2 && n_ant <= kPeelMaxAnt && gain_smem_bytes(n_ant, false, 1024) <= kPeelSmemMax;
 }
 
 size_t gain_cell_bytes(int n_ant) { return (size_t)n_ant * n_ant * (sizeof(double2) + sizeof(double)); }
@@ -340,19 +351,12 @@ hipError_t launch_gain(const GainArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_gain_prep, dim3(prep_blocks), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)a.ncell), block(kGainThreads);
-  const bool w64 = gain_smem_bytes(a.n_ant, true) <= kPeelSmemMax;
-  const size_t sm = gain_smem_bytes(a.n_ant, w64);
-  if (w64) {
-    e = hipFuncSetAttribute((const void *)k_gain_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gain_solve<double>, grid, block, sm, s, a);
-  } else {
-    e = hipFuncSetAttribute((const void *)k_gain_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gain_solve<float>, grid, block, sm, s, a);
-  }
-  return hipGetLastError();
+  // FP64 W while it fits; with a.w32 (allowed by the caller) and when two
+  // 512-thread cells then fit in one CU's LDS, FP32 W and two cells per CU
+  // (their conjugate-gradient steps interleave: the solve is latency-bound)
+  if (a.w32 && 2 * gain_smem_bytes(a.n_ant, false, 512) <= kPeelSmemMax) return launch_solve<float, 512>(a, s);
+  if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024>(a, s);
+  return launch_solve<float, 1024>(a, s);
 }
 
 }  // namespace vp

@@ -163,7 +163,6 @@ constexpr int kProfClasses = 4;
 // Peel calibration (vp_calib.hip).
 constexpr int kPeelMaxAnt = 256;          // tiles per observation (one thread each)
 constexpr size_t kPeelSmemMax = 163840;  // LDS per workgroup on gfx950
-constexpr int kGainThreads = 1024;       // threads per cell of the gain solve
 constexpr size_t kPeelWsMax = size_t(1) << 30;  // per-cell tables of one launch, bytes (at least one cell)
 
 struct GainArgs {
@@ -181,6 +180,7 @@ struct GainArgs {
   int cell0, ncell;       // the launch covers cells cell0 .. cell0 + ncell - 1 (cell = t K + k)
   double2 *xt;            // workspace [ncell][n_ant][n_ant]
   double *wf;             // workspace [ncell][n_ant][n_ant]
+  int w32;                // 1: the step's operator may hold W in FP32 (the right-hand side stays FP64)
 };
 
 // Host-side launchers (vp_kernels.hip).
@@ -195,7 +195,7 @@ hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks,
 hipError_t serve_grid(int *grid);
 hipError_t launch_gain(const GainArgs &a, hipStream_t s);
 bool gain_supported(int n_ant);
-size_t gain_smem_bytes(int n_ant, bool w64);
+size_t gain_smem_bytes(int n_ant, bool w64, int threads);
 size_t gain_cell_bytes(int n_ant);  // workspace bytes per cell
 
 // sizes of per-shapelet tile storage

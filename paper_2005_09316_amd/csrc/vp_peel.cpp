@@ -116,6 +116,8 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   a.comp = a.pair_bl + npairs;
   a.gains = (double2 *)gains_dev;
   a.subtract = 1;
+  // the FP64 path keeps the operator in FP64 where it fits
+  a.w32 = precision != VP_PREC_FP64;
   a.xt = (double2 *)w.ws;
   a.wf = (double *)((char *)w.ws + (size_t)chunk * n_ant * n_ant * sizeof(double2));
   {
