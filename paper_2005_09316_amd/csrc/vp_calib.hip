@@ -351,9 +351,11 @@ hipError_t launch_gain(const GainArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_gain_prep, dim3(prep_blocks), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // FP64 W while it fits; with a.w32 (allowed by the caller) and when two
-  // 512-thread cells then fit in one CU's LDS, FP32 W and two cells per CU
-  // (their conjugate-gradient steps interleave: the solve is latency-bound)
+  // FP64 W while it fits; with a.w32 (allowed by the caller), FP32 W and
+  // smaller cells, three (256 threads) or two (512 threads) sharing one CU's
+  // LDS, so that their conjugate-gradient steps interleave (the solve is
+  // latency-bound)
+  if (a.w32 && 3 * gain_smem_bytes(a.n_ant, false, 256) <= kPeelSmemMax) return launch_solve<float, 256>(a, s);
   if (a.w32 && 2 * gain_smem_bytes(a.n_ant, false, 512) <= kPeelSmemMax) return launch_solve<float, 512>(a, s);
   if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024>(a, s);
   return launch_solve<float, 1024>(a, s);
