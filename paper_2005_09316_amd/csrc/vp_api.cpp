@@ -298,7 +298,6 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.subtract = subtract;
   a.c64 = dtype == VP_C64;
   a.conj = obs->sign < 0;
-  a.nb = 0;
   a.n_rb = (int)((a.nrows + kTileRows - 1) / kTileRows);
   a.n_cb = obs->Kpad / kPgChan;
   a.lut = lut;

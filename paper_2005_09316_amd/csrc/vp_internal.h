@@ -113,7 +113,6 @@ struct TileArgs {
   int subtract;        // 0: vis = V; 1: vis = vis - V
   int c64;             // 1: complex64, 0: complex128
   int conj;            // 1 when the exponent sign is -1
-  int nb;              // FP64 shapelet kernel: order bucket
   const float *lut;    // basis table of the lookup-table variant, or null
   double dfk;          // (nu_{k+1} - nu_k) / c when the channels are uniformly spaced
   int uniform;         // 1: channels uniformly spaced (the mixed path rotates phasors by dfk)

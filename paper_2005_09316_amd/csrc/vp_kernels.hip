@@ -983,7 +983,7 @@ __device__ __forceinline__ double lut_at(const LutPos &q, int n) {
   return (double)((n & 1) ? q.odd * v : v);
 }
 
-template <int NB, bool LUT>
+template <bool LUT>
 __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
   constexpr int KB = kShpChan;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1005,58 +1005,66 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
       const double xa = f * fma(fr[0], u, fma(fr[1], v, fr[2] * w));
       const double xb = f * fma(fr[3], u, fma(fr[4], v, fr[5] * w));
       const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
-      double pb[NB + 8];
-      if constexpr (LUT) {
-        const LutPos qb = lut_pos(a.lut, xb);
-#pragma unroll
-        for (int n = 0; n < NB + 8; ++n) pb[n] = n <= kNmaxLimit ? lut_at(qb, n) : 0.0;
-      } else {
-        const double sx = 1.41421356237309504880 * xb;
-        pb[0] = kPiM14 * exp(-0.5 * xb * xb);
-        double pm1 = 0.0;
-#pragma unroll
-        for (int n = 0; n < NB + 7; ++n) {
-          const double nx = herm_step<double>(sx, pb[n], pm1, n);
-          pm1 = pb[n];
-          pb[n + 1] = nx;
-        }
-      }
+      // The second axis in chunks of 32 orders (its recurrence carried
+      // across chunks); per chunk the first axis is walked from order 0 and
+      // each row n1 is dotted with the chunk's part of row n1 of the signed
+      // coefficient matrix.  32 values per lane stay in registers.
       const double *C = a.t.c64 + a.t.c64_off[j];
       const int ld = a.t.c64_ld[j];
-      const double sx = 1.41421356237309504880 * xa;
-      double pa = kPiM14 * exp(-0.5 * xa * xa), pam1 = 0.0;
-      LutPos qa;
+      const double sxa = 1.41421356237309504880 * xa, sxb = 1.41421356237309504880 * xb;
+      LutPos qa, qb;
       if constexpr (LUT) {
         qa = lut_pos(a.lut, xa);
-        pa = lut_at(qa, 0);
+        qb = lut_pos(a.lut, xb);
       }
+      double bn = kPiM14 * exp(-0.5 * xb * xb), bm1 = 0.0;  // second-axis recurrence state
       double xr = 0.0, xi = 0.0;
-      for (int n1 = 0; n1 <= N; ++n1) {
-        const double *Cr = C + (int64_t)n1 * ld;
-        double te = 0.0, to = 0.0;
+      for (int ch = 0; 32 * ch <= N; ++ch) {
+        const int m0 = 32 * ch;
+        double pb[32];
 #pragma unroll
-        for (int b8 = 0; b8 < (NB + 8) / 8; ++b8) {
-          if (8 * b8 <= N - n1) {
-#pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-              te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
-              to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
-            }
+        for (int i = 0; i < 32; ++i) {
+          if constexpr (LUT) {
+            pb[i] = m0 + i <= kNmaxLimit ? lut_at(qb, m0 + i) : 0.0;
+          } else {
+            pb[i] = bn;
+            const double nx = herm_step<double>(sxb, bn, bm1, m0 + i);  // orders <= 127: table size
+            bm1 = bn;
+            bn = nx;
           }
         }
-        if (n1 & 1) {
-          xr = fma(pa, to, xr);
-          xi = fma(pa, te, xi);
-        } else {
-          xr = fma(pa, te, xr);
-          xi = fma(pa, to, xi);
-        }
-        if constexpr (LUT) {
-          pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
-        } else {
-          const double nx = herm_step<double>(sx, pa, pam1, n1);
-          pam1 = pa;
-          pa = nx;
+        double pa, pam1 = 0.0;
+        if constexpr (LUT)
+          pa = lut_at(qa, 0);
+        else
+          pa = kPiM14 * exp(-0.5 * xa * xa);
+        for (int n1 = 0; n1 <= N - m0; ++n1) {
+          const double *Cr = C + (int64_t)n1 * ld + m0;
+          double te = 0.0, to = 0.0;
+#pragma unroll
+          for (int b8 = 0; b8 < 4; ++b8) {
+            if (8 * b8 <= N - m0 - n1) {
+#pragma unroll
+              for (int e = 0; e < 8; e += 2) {
+                te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
+                to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
+              }
+            }
+          }
+          if (n1 & 1) {
+            xr = fma(pa, to, xr);
+            xi = fma(pa, te, xi);
+          } else {
+            xr = fma(pa, te, xr);
+            xi = fma(pa, to, xi);
+          }
+          if constexpr (LUT) {
+            pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
+          } else {
+            const double nx = herm_step<double>(sxa, pa, pam1, n1);
+            pam1 = pa;
+            pa = nx;
+          }
         }
       }
       double cs, sn;
@@ -1341,25 +1349,11 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) 
   const dim3 g((unsigned)nt), b(kTileRows);
   switch (prec) {
     case kFP64:
-      if (max_nmax <= 16)
-        hipLaunchKernelGGL((k_shp_fp64<16, false>), g, b, 0, s, a);
-      else if (max_nmax <= 32)
-        hipLaunchKernelGGL((k_shp_fp64<32, false>), g, b, 0, s, a);
-      else if (max_nmax <= 64)
-        hipLaunchKernelGGL((k_shp_fp64<64, false>), g, b, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_shp_fp64<96, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL(k_shp_fp64<false>, g, b, 0, s, a);
       break;
     case kLut:
       if (!a.lut) return hipErrorInvalidValue;
-      if (max_nmax <= 16)
-        hipLaunchKernelGGL((k_shp_fp64<16, true>), g, b, 0, s, a);
-      else if (max_nmax <= 32)
-        hipLaunchKernelGGL((k_shp_fp64<32, true>), g, b, 0, s, a);
-      else if (max_nmax <= 64)
-        hipLaunchKernelGGL((k_shp_fp64<64, true>), g, b, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_shp_fp64<96, true>), g, b, 0, s, a);
+      hipLaunchKernelGGL(k_shp_fp64<true>, g, b, 0, s, a);
       break;
     case kFP32:
       hipLaunchKernelGGL((k_shp_mfma<float, float, kCmF32>), g, b, 0, s, a);
