@@ -70,7 +70,7 @@ SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 8, 12, 3
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (summary in
 # profiles/k_pg_tile_mwa-like_hbm-traffic.md), valid for the kernel source
 # whose hash is recorded; reported as null once that source changes.
-PG_TRAFFIC = {"bytes": 116.5e6 + 29.1e6, "source_sha256_16": "223b45b9c1efd87b"}
+PG_TRAFFIC = {"bytes": 119.2e6 + 29.1e6, "source_sha256_16": "f4d873f40acd2f2c"}
 
 
 # dense MFMA peaks and the FP64 vector peak (TFLOP/s)

@@ -305,7 +305,8 @@ struct PgSmem {
 template <int PREC, bool UNI = false>
 __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
                                         PgSmem<typename PgTypes<PREC>::acc_t> &sm) {
-  static_assert(!UNI || (PREC == kMixed && kPgChan == 8), "channel rotation is a mixed-path, 8-channel scheme");
+  static_assert(!UNI || ((PREC == kMixed || PREC == kFP64) && kPgChan == 8),
+                "channel rotation: mixed and FP64 paths, 8-channel tiles");
   typedef typename PgTypes<PREC>::acc_t acc_t;
   constexpr int KB = kPgChan;
   double4 *s_pos = sm.pos;
@@ -377,7 +378,32 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
           else
             Q = fmaf((float)g.x, (float)uu, fmaf((float)g.y, (float)vv, (float)g.z * (float)uv));
         }
-        if (PREC == kFP64) {
+        if (PREC == kFP64 && UNI) {
+          // the rotation scheme in FP64 (one rotation adds ~2e-16)
+          const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
+          double c[KB], s[KB], cd, sd;
+          turns_sincos_f64(t0 * f[0], c[0], s[0]);
+          turns_sincos_f64(t0 * fa3, c[3], s[3]);
+          turns_sincos_f64(t0 * fa6, c[6], s[6]);
+          turns_sincos_f64(t0 * a.dfk, cd, sd);
+          c[1] = fma(c[0], cd, -s[0] * sd);
+          s[1] = fma(s[0], cd, c[0] * sd);
+          c[4] = fma(c[3], cd, -s[3] * sd);
+          s[4] = fma(s[3], cd, c[3] * sd);
+          c[7] = fma(c[6], cd, -s[6] * sd);
+          s[7] = fma(s[6], cd, c[6] * sd);
+          c[2] = fma(c[3], cd, s[3] * sd);
+          s[2] = fma(s[3], cd, -c[3] * sd);
+          c[5] = fma(c[6], cd, s[6] * sd);
+          s[5] = fma(s[6], cd, -c[6] * sd);
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            double S = (double)s_flux[jj][k];
+            if (kind == 1) S *= exp2(-(double)Q * (f[k] * f[k]));
+            prt_re[k] = fma(S, c[k], (double)prt_re[k]);
+            prt_im[k] = fma(S, s[k], (double)prt_im[k]);
+          }
+        } else if (PREC == kFP64) {
           const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
@@ -1324,7 +1350,11 @@ hipError_t launch_pg(const TileArgs &a, int prec, hipStream_t s) {
   if (nt > 0x7fffffff) return hipErrorInvalidValue;
   switch (prec) {
     case kFP64:
-      hipLaunchKernelGGL(k_pg_tile<kFP64>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+    case kLut:  // the lookup-table variant differs from the FP64 path in the shapelet basis only
+      if (a.uniform)
+        hipLaunchKernelGGL((k_pg_tile<kFP64, true>), dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_pg_tile<kFP64, false>), dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
       break;
     case kFP32:
       hipLaunchKernelGGL(k_pg_tile<kFP32>, dim3((unsigned)nt), dim3(kTileRows), 0, s, a);
