@@ -368,7 +368,8 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
           s_flux[jj][k] = (acc_t)a.d.flux32[fi];
       }
       __syncthreads();
-      for (int jj = 0; jj < n; ++jj) {
+      // one component's terms into the plain partial sums
+      auto term = [&](int jj) {
         const double4 p = s_pos[jj];
         acc_t Q = 0;
         if (kind == 1) {
@@ -462,19 +463,30 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
             prt_im[k] = fmaf(S, s, (float)prt_im[k]);
           }
         }
-        if ((jj & (kFlush - 1)) == kFlush - 1 || jj == n - 1) {
+      };
+      auto flush_partials = [&]() {
 #pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            if constexpr (PREC == kMixed) {
-              dsum_re[k] += (double)prt_re[k];
-              dsum_im[k] += (double)prt_im[k];
-            } else {
-              kahan_add(sum_re[k], cmp_re[k], prt_re[k]);
-              kahan_add(sum_im[k], cmp_im[k], prt_im[k]);
-            }
-            prt_re[k] = prt_im[k] = 0;
+        for (int k = 0; k < KB; ++k) {
+          if constexpr (PREC == kMixed) {
+            dsum_re[k] += (double)prt_re[k];
+            dsum_im[k] += (double)prt_im[k];
+          } else {
+            kahan_add(sum_re[k], cmp_re[k], prt_re[k]);
+            kahan_add(sum_im[k], cmp_im[k], prt_im[k]);
           }
+          prt_re[k] = prt_im[k] = 0;
         }
+      };
+      // groups of kFlush components, unrolled, then the remainder
+      int jg = 0;
+      for (; jg + kFlush <= n; jg += kFlush) {
+#pragma unroll
+        for (int jo = 0; jo < kFlush; ++jo) term(jg + jo);
+        flush_partials();
+      }
+      if (jg < n) {
+        for (int jj = jg; jj < n; ++jj) term(jj);
+        flush_partials();
       }
     }
   }
