@@ -56,21 +56,25 @@ if ROOT not in sys.path:
 
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic VALU issue slots per evaluation (transcendentals issue at half rate).
+# Algorithmic VALU issue slots per evaluation.  Every VALU instruction of a wave
+# of 64 takes one 4-cycle issue slot of its SIMD; v_sin/v_cos/v_exp take one slot
+# too and then run in the transcendental unit beside the vector ALU (measured: the
+# kernel's VALU instructions, transcendentals included, fill 0.99 of the SIMD
+# cycles at 4 cycles each, so they do not hold the issue port longer).
 # With uniformly spaced channels (this workload) the mixed kernel evaluates the
 # phasor of 3 channels of each 8 and the channel step, and rotates the others:
-#   per 8 channels: 4 x (phase scale 1 + reduction 1 + convert 1 + sin 2 + cos 2)
-#                   + 5 complex rotations x 4 + 8 complex MACs x 2 = 64
-#   point:    64 / 8                                                       = 8
-#   Gaussian: point + exponent scale 1 + exp2 2 + flux x envelope 1        = 12
+#   per 8 channels: 4 x (phase scale 1 + reduction 1 + convert 1 + sin 1 + cos 1)
+#                   + 5 complex rotations x 4 + 8 complex MACs x 2 = 56
+#   point:    56 / 8                                                       = 7
+#   Gaussian: point + exponent scale 1 + exp2 1 + flux x envelope 1        = 10
 #   per (row, component): u l + v m + w (n - 1), 3 FMAs shared by the row's channels
-SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 8, 12, 3
+SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 7, 10, 3
 
 # HBM bytes per launch of the point/Gaussian kernel on this workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (summary in
 # profiles/k_pg_tile_mwa-like_hbm-traffic.md), valid for the kernel source
 # whose hash is recorded; reported as null once that source changes.
-PG_TRAFFIC = {"bytes": 119.2e6 + 29.1e6, "source_sha256_16": "f4d873f40acd2f2c"}
+PG_TRAFFIC = {"bytes": 129.7e6 + 29.1e6, "source_sha256_16": "4b21b4cb7e8eb9dd"}
 
 
 # dense MFMA peaks and the FP64 vector peak (TFLOP/s)
