@@ -303,8 +303,12 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.lut = lut;
   a.dfk = obs->dfk;
   a.uniform = obs->uniform;
-  hipError_t e;
-  {
+  // A sky of shapelets only skips the point/Gaussian pass, which would only
+  // write zeros (predict) or rewrite the data unchanged (subtract).
+  const bool pg_pass = sky->P + sky->G > 0 || sky->S == 0;
+  a.fresh = !pg_pass && !subtract;
+  hipError_t e = hipSuccess;
+  if (pg_pass) {
     ProfScope ps(ctx, stream, 1);
     e = launch_pg(a, precision, stream);
   }

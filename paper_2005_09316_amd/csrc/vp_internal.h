@@ -116,6 +116,8 @@ struct TileArgs {
   const float *lut;    // basis table of the lookup-table variant, or null
   double dfk;          // (nu_{k+1} - nu_k) / c when the channels are uniformly spaced
   int uniform;         // 1: channels uniformly spaced (the mixed path rotates phasors by dfk)
+  int fresh;           // 1: the shapelet pass starts from zero instead of reading vis (a
+                       //    predict with no point/Gaussian pass before it)
 };
 
 // ---------------------------------------------------------------------------

@@ -704,11 +704,11 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
   const int64_t rowc = valid ? row : a.nrows - 1;
   const int K = a.K;
 
-  // sums start from what the point/Gaussian pass left
+  // sums start from what the point/Gaussian pass left (from zero without one)
 #pragma unroll
   for (int c = 0; c < KB; ++c) {
     double sr = 0, si = 0;
-    if (valid && k0 + c < K) {
+    if (valid && k0 + c < K && !a.fresh) {
       const int64_t idx = row * K + k0 + c;
       if (a.c64) {
         const float2 x = ((const float2 *)a.vis)[idx];
@@ -1115,8 +1115,10 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
       const int64_t idx = row * a.K + k0 + c;
       double2 *o = (double2 *)a.vis;
       float2 *o32 = (float2 *)a.vis;
-      double xr, xi;
-      if (a.c64) {
+      double xr = 0.0, xi = 0.0;
+      if (a.fresh) {
+        // no point/Gaussian pass wrote this visibility
+      } else if (a.c64) {
         const float2 x = o32[idx];
         xr = x.x;
         xi = a.conj ? -x.y : x.y;

@@ -164,6 +164,7 @@ static int admit(Scheduler *s, JobRec *j) {
   a.n_cb = obs->Kpad / kPgChan;
   a.dfk = obs->dfk;
   a.uniform = obs->uniform;
+  a.fresh = 0;
   const int slot = s->free_slots.back();
   s->free_slots.pop_back();
   j->slot = slot;

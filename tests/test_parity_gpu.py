@@ -48,13 +48,18 @@ def _case(name):
         freqs = np.sort(rng.uniform(170e6, 190e6, 11))
         return synth.make_config(1, n_tiles=20, n_time=2, n_chan=11, n_point=200, n_gauss=40,
                                  shapelet_nmax=[20], freq_hz=freqs)
+    if name == "lobes-only":
+        # shapelets only: no point/Gaussian pass runs, the shapelet pass starts
+        # from zero (the output buffer holds NaN before a predict)
+        obs, sky = synth.make_config(2, n_tiles=20, n_time=2, n_chan=6)
+        return obs, synth.select_components(sky, points=[], gauss=[])
     if name == "nmax-limit":
         return synth.make_config(0, n_tiles=16, n_time=2, n_chan=5, n_point=3, n_gauss=2,
                                  shapelet_nmax=[96, 0, 1, 31, 32, 63, 64])
     raise KeyError(name)
 
 
-CASES = ["tiny", "mwa-mid", "fornax-mid", "mwa-nonuniform", "nmax-limit"]
+CASES = ["tiny", "mwa-mid", "fornax-mid", "lobes-only", "mwa-nonuniform", "nmax-limit"]
 _REF = {}
 
 
