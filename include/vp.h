@@ -226,10 +226,13 @@ int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes);
  * ant1, ant2: host arrays [n_bl] (n_bl of obs), the tiles (0..n_ant-1,
  * distinct, each pair at most once) of each baseline, the same for every
  * time step; read during the call only.
- * precision selects the path of the model prediction, and of the solve's
- * normal-equation weights |I|^2: FP64 for VP_PREC_FP64 (while they fit in
- * LDS, up to 183 tiles), FP32 otherwise -- the right-hand side, and so the
- * solution the iterations converge to, is FP64 either way.
+ * precision selects the path of the model prediction and of the solve.
+ * VP_PREC_FP64: the per-cell tables (X = I^* V seen from each tile, and
+ * |I|^2) in FP64, the step's normal-equation weights |I|^2 in FP64 while
+ * they fit in LDS (up to 183 tiles) and FP32 beyond; the right-hand side,
+ * and so the solution the iterations converge to, is FP64.  Any other
+ * precision: the tables and the weights in FP32, sums and steps in FP64;
+ * the solution moves by the tables' FP32 rounding (about 1e-7 relative).
  * gains_dev: caller-owned device memory [n_time][n_chan][n_ant] complex128
  * receiving the gains, or NULL.  data_dev as for vp_subtract.  Asynchronous
  * on hip_stream; calls on one context share a workspace of n_time x n_bl x

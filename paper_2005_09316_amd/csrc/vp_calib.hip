@@ -19,12 +19,16 @@
 // own size that the iteration amplifies into a drift of the global phase.
 // The solve also stops once the residual is at the rounding level of r.
 // With X_ko = I^* V seen from tile k (a per-cell table built once), the
-// right-hand side is r_k = sum_o g_o X_ko - g_k D_k; X and W stream from
-// HBM once per Gauss-Newton iteration as full n x n tables, coalesced over
-// k.  For the conjugate-gradient products W sits in LDS, packed, in FP64
-// while it fits (up to 183 tiles) and in FP32 beyond: that changes the
+// right-hand side is r_k = sum_o g_o X_ko - g_k D_k; X streams from HBM once
+// per Gauss-Newton iteration as a full n x n table, coalesced over k.  For
+// the conjugate-gradient products W sits in LDS, packed.  On the FP64 path
+// the tables are FP64, D_k is summed from the FP64 W table, and W in LDS is
+// FP64 while it fits (up to 183 tiles) and FP32 beyond: that changes the
 // step's operator at the 1e-7 level, not the right-hand side, so not the
-// fixed point.
+// fixed point.  On the mixed path the tables hold X and W rounded to FP32
+// (sums and steps stay FP64) and D_k comes from the LDS copy of W: the
+// solution moves by the tables' rounding, ~1e-7 relative, and the
+// right-hand side pass reads 8 bytes per tile pair instead of 24.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -82,33 +86,73 @@ __device__ __forceinline__ double2 gauge_project(double2 v, double2 gk, int k, i
   return v;
 }
 
+// Table element types: TT (FP64 or FP32) and its complex pair.
+template <typename TT>
+struct TabPair;
+template <>
+struct TabPair<float> {
+  typedef float2 type;
+};
+template <>
+struct TabPair<double> {
+  typedef double2 type;
+};
+
+// Cells per workgroup of the table kernel (48 KB of LDS either way).
+template <typename TT>
+constexpr int tab_cells() {
+  return sizeof(TT) == sizeof(float) ? 16 : 8;
+}
+
 // Per-cell tables for the solve, from the [T][B][K] model and data:
 //   xt [cell][o][k] = X_ko: I_b^* V_b for k = ant1, o = ant2 of baseline b,
-//                     its conjugate for k = ant2, o = ant1 (zero elsewhere:
-//                     the caller clears the table);
-//   wf [cell][o][k] = |I_b|^2 for both orders of the baseline's tiles
-//                     (zero elsewhere: the caller clears it too).
-// Consecutive threads take consecutive cells of one baseline, i.e. adjacent
-// channels: the reads are coalesced.
-__global__ __launch_bounds__(256) void k_gain_prep(GainArgs a) {
-  const int n = a.n_ant;
-  const int64_t total = (int64_t)a.ncell * a.B;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int cl = (int)(e % a.ncell), b = (int)(e / a.ncell);
-    const int cell = a.cell0 + cl, t = cell / a.K, kc = cell % a.K;
-    const int64_t i = ((int64_t)t * a.B + b) * a.K + kc;
-    const double2 m = load_vis(a.model, a.c64, i);
-    const double2 v = load_vis(a.data, a.c64, i);
-    const int i1 = a.ant1[b], i2 = a.ant2[b];
-    const double2 x = cmul(cconj(m), v);
-    double2 *xc = a.xt + (int64_t)cl * n * n;
-    xc[(int64_t)i2 * n + i1] = x;
-    xc[(int64_t)i1 * n + i2] = cconj(x);
-    double *wc = a.wf + (int64_t)cl * n * n;
-    const double w2 = m.x * m.x + m.y * m.y;
-    wc[(int64_t)i2 * n + i1] = w2;
-    wc[(int64_t)i1 * n + i2] = w2;
+//                     its conjugate for k = ant2, o = ant1;
+//   wf [cell][o][k] = |I_b|^2 for both orders of the baseline's tiles;
+// zero on the diagonal and for tile pairs without a baseline.  Workgroup
+// (x, o) writes row o of the tables of C = tab_cells consecutive cells: the
+// row's baselines are read C adjacent channels at a time (contiguous in the
+// [T][B][K] layout), staged in LDS, and written one row after another
+// (contiguous), every entry once, so no clearing pass is needed.  Each
+// baseline is read twice, once for the row of either tile.
+template <typename TT>
+__global__ __launch_bounds__(256) void k_gain_tables(GainArgs a) {
+  typedef typename TabPair<TT>::type TT2;
+  constexpr int C = tab_cells<TT>();
+  __shared__ TT2 sx[C][kPeelMaxAnt];
+  __shared__ TT sw[C][kPeelMaxAnt];
+  const int n = a.n_ant, o = blockIdx.y;
+  const int c0 = blockIdx.x * C;
+  const int nc = min(C, a.ncell - c0);
+  for (int e = threadIdx.x; e < nc * n; e += 256) {
+    const int j = e % nc, k = e / nc;
+    TT2 x;
+    x.x = 0;
+    x.y = 0;
+    TT w = 0;
+    const int b = k == o ? -1 : a.pair_bl[pair_index(n, min(o, k), max(o, k))];
+    if (b >= 0) {
+      const int cell = a.cell0 + c0 + j, t = cell / a.K, kc = cell % a.K;
+      const int64_t i = ((int64_t)t * a.B + b) * a.K + kc;
+      const double2 m = load_vis(a.model, a.c64, i);
+      const double2 v = load_vis(a.data, a.c64, i);
+      // I^* V with k = ant1, o = ant2; its conjugate for the other order
+      double2 xv = cmul(cconj(m), v);
+      if (a.ant1[b] == o) xv = cconj(xv);
+      x.x = (TT)xv.x;
+      x.y = (TT)xv.y;
+      w = (TT)(m.x * m.x + m.y * m.y);
+    }
+    sx[j][k] = x;
+    sw[j][k] = w;
+  }
+  __syncthreads();
+  TT2 *X = (TT2 *)a.xt;
+  TT *W = (TT *)a.wf;
+  for (int e = threadIdx.x; e < nc * n; e += 256) {
+    const int j = e / n, k = e - j * n;
+    const int64_t off = ((int64_t)(c0 + j) * n + o) * n + k;
+    X[off] = sx[j][k];
+    W[off] = sw[j][k];
   }
 }
 
@@ -145,10 +189,13 @@ __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
 // thread of tile k holds the tile's gain and its conjugate-gradient state.
 // W sits in LDS packed with its zero diagonal, as WT.  The operator of the
 // step uses these W values for its diagonal too, so that i g stays its
-// exact null vector; the right-hand side uses the FP64 tables.  The solve
-// is conjugate gradients preconditioned by that diagonal (Jacobi).
-template <typename WT, int NT>
+// exact null vector; the right-hand side uses the tables (TT), and with
+// FP32 tables that same LDS copy of W for D.  The solve is conjugate
+// gradients preconditioned by that diagonal (Jacobi).
+template <typename WT, int NT, typename TT>
 __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
+  typedef typename TabPair<TT>::type TT2;
+  constexpr bool tab64 = sizeof(TT) == sizeof(double);
   extern __shared__ __align__(16) unsigned char smem[];
   double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
   double2 *y = g + kPeelMaxAnt;                   // [kPeelMaxAnt] g_o p_o^* of the current direction
@@ -173,8 +220,8 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   const int pl0 = packed_index(n, o0 < kr ? o0 : 0, kr);
   const int ph0 = packed_index(n, kr, o0 > kr ? o0 : kr);
 
-  const double2 *X = a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
-  const double *Wf = a.wf + (int64_t)cl * n * n;  // |I|^2 [o n + k], FP64, zero for o == k
+  const TT2 *X = (const TT2 *)a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
+  const TT *Wf = (const TT *)a.wf + (int64_t)cl * n * n;    // |I|^2 [o n + k], zero for o == k
   for (int idx = tid; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx - i * n;
     if (i <= j) W[packed_index(n, i, j)] = (WT)Wf[idx];
@@ -210,20 +257,21 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   };
 
   for (int it = 0; it < a.n_iter; ++it) {
-    // r_k = sum_o g_o X_ko - g_k D_k,  D_k = sum_o W_ko |g_o|^2 in FP64;
-    // Dt_k: the same sum over the LDS copy of W
+    // r_k = sum_o g_o X_ko - g_k D_k,  D_k = sum_o W_ko |g_o|^2 in FP64
+    // (FP64 tables) or Dt_k, the same sum over the LDS copy of W
     double2 sx = make_double2(0.0, 0.0);
     double sd = 0.0, sa = 0.0;  // sa: sum of |g_o X_ko|, for the rounding level of r_k
     if (row) {
 #pragma unroll 2
       for (int o = o0; o < o1; ++o) {
         const double2 go = g[o];
-        const double2 x = X[(int64_t)o * n + k];
+        const TT2 xt = X[(int64_t)o * n + k];
+        const double2 x = make_double2(xt.x, xt.y);
         const double g2 = go.x * go.x + go.y * go.y;
         sx.x += go.x * x.x - go.y * x.y;
         sx.y += go.x * x.y + go.y * x.x;
         sa += sqrt(g2 * (x.x * x.x + x.y * x.y));
-        sd += g2 * Wf[(int64_t)o * n + k];
+        if constexpr (tab64) sd += g2 * Wf[(int64_t)o * n + k];
       }
     }
     const double sdt = wdot(g, true).x;
@@ -250,6 +298,7 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
     __syncthreads();
     if (own) {
       for (int q = 0; q < parts; ++q) Dt += pa[q * nk + k].x;
+      if constexpr (!tab64) D = Dt;
       r.x -= gk.x * D;
       r.y -= gk.y * D;
       scale += sqrt(gk.x * gk.x + gk.y * gk.y) * D;
@@ -323,13 +372,21 @@ size_t gain_smem_bytes(int n_ant, bool w64, int threads) {
          (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
 }
 
-template <typename WT, int NT>
+template <typename WT, int NT, typename TT>
 static hipError_t launch_solve(const GainArgs &a, hipStream_t s) {
   const size_t sm = gain_smem_bytes(a.n_ant, sizeof(WT) == sizeof(double), NT);
-  hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<WT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sm);
+  hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<WT, NT, TT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gain_solve<WT, NT>), dim3((unsigned)a.ncell), dim3(NT), sm, s, a);
+  hipLaunchKernelGGL((k_gain_solve<WT, NT, TT>), dim3((unsigned)a.ncell), dim3(NT), sm, s, a);
+  return hipGetLastError();
+}
+
+template <typename TT>
+static hipError_t launch_tables(const GainArgs &a, hipStream_t s) {
+  constexpr int C = tab_cells<TT>();
+  hipLaunchKernelGGL(k_gain_tables<TT>, dim3((unsigned)((a.ncell + C - 1) / C), (unsigned)a.n_ant), dim3(256), 0, s,
+                     a);
   return hipGetLastError();
 }
 
@@ -337,28 +394,28 @@ bool gain_supported(int n_ant) {
   return n_ant >= 2 && n_ant <= kPeelMaxAnt && gain_smem_bytes(n_ant, false, 1024) <= kPeelSmemMax;
 }
 
-size_t gain_cell_bytes(int n_ant) { return (size_t)n_ant * n_ant * (sizeof(double2) + sizeof(double)); }
+size_t gain_cell_bytes(int n_ant, bool w32) {
+  return (size_t)n_ant * n_ant * (w32 ? sizeof(float2) + sizeof(float) : sizeof(double2) + sizeof(double));
+}
 
 hipError_t launch_gain(const GainArgs &a, hipStream_t s) {
   if (a.ncell <= 0) return hipSuccess;
   if (!gain_supported(a.n_ant) || a.cell0 < 0 || (int64_t)a.cell0 + a.ncell > (int64_t)a.T * a.K)
     return hipErrorInvalidValue;
-  hipError_t e = hipMemsetAsync(a.xt, 0, (size_t)a.ncell * a.n_ant * a.n_ant * sizeof(double2), s);
-  if (e == hipSuccess) e = hipMemsetAsync(a.wf, 0, (size_t)a.ncell * a.n_ant * a.n_ant * sizeof(double), s);
+  hipError_t e = a.w32 ? launch_tables<float>(a, s) : launch_tables<double>(a, s);
   if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)a.ncell * a.B;
-  const unsigned prep_blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gain_prep, dim3(prep_blocks), dim3(256), 0, s, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // FP64 W while it fits; with a.w32 (allowed by the caller), FP32 W and
-  // smaller cells, three (256 threads) or two (512 threads) sharing one CU's
-  // LDS, so that their conjugate-gradient steps interleave (the solve is
-  // latency-bound)
-  if (a.w32 && 3 * gain_smem_bytes(a.n_ant, false, 256) <= kPeelSmemMax) return launch_solve<float, 256>(a, s);
-  if (a.w32 && 2 * gain_smem_bytes(a.n_ant, false, 512) <= kPeelSmemMax) return launch_solve<float, 512>(a, s);
-  if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024>(a, s);
-  return launch_solve<float, 1024>(a, s);
+  // FP64 W while it fits; with a.w32 (the mixed path), FP32 tables, FP32 W
+  // and smaller cells, three (256 threads) or two (512 threads) sharing one
+  // CU's LDS, so that their conjugate-gradient steps interleave (the solve
+  // is latency-bound)
+  if (a.w32) {
+    if (3 * gain_smem_bytes(a.n_ant, false, 256) <= kPeelSmemMax) return launch_solve<float, 256, float>(a, s);
+    if (2 * gain_smem_bytes(a.n_ant, false, 512) <= kPeelSmemMax) return launch_solve<float, 512, float>(a, s);
+    if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024, float>(a, s);
+    return launch_solve<float, 1024, float>(a, s);
+  }
+  if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024, double>(a, s);
+  return launch_solve<float, 1024, double>(a, s);
 }
 
 }  // namespace vp

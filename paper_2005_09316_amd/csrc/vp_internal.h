@@ -179,9 +179,9 @@ struct GainArgs {
   double2 *gains;         // [T][K][n_ant] output, or null
   int subtract;
   int cell0, ncell;       // the launch covers cells cell0 .. cell0 + ncell - 1 (cell = t K + k)
-  double2 *xt;            // workspace [ncell][n_ant][n_ant]
-  double *wf;             // workspace [ncell][n_ant][n_ant]
-  int w32;                // 1: the step's operator may hold W in FP32 (the right-hand side stays FP64)
+  void *xt;               // workspace [ncell][n_ant][n_ant] complex X (float2 when w32, else double2)
+  void *wf;               // workspace [ncell][n_ant][n_ant] |I|^2 (float when w32, else double)
+  int w32;                // 1 (mixed path): FP32 tables and FP32 W in the step's operator, FP64 sums
 };
 
 // Host-side launchers (vp_kernels.hip).
@@ -197,7 +197,7 @@ hipError_t serve_grid(int *grid);
 hipError_t launch_gain(const GainArgs &a, hipStream_t s);
 bool gain_supported(int n_ant);
 size_t gain_smem_bytes(int n_ant, bool w64, int threads);
-size_t gain_cell_bytes(int n_ant);  // workspace bytes per cell
+size_t gain_cell_bytes(int n_ant, bool w32);  // workspace bytes per cell
 
 // sizes of per-shapelet tile storage
 inline int64_t a32_floats(int nmax) { return (int64_t)shp_pairs(nmax) * kA32PerPair; }

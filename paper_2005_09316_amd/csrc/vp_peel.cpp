@@ -73,7 +73,9 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   if (e != hipSuccess) return hip_error(e, "waiting for the previous peel");
   const size_t mbytes = (size_t)obs->T * B * obs->K * (dtype == VP_C64 ? 8 : 16);
   const int64_t cells = (int64_t)obs->T * obs->K;
-  const size_t cell_bytes = gain_cell_bytes(n_ant);
+  // the FP64 path keeps its tables and the operator in FP64 (the latter where it fits)
+  const bool w32 = precision != VP_PREC_FP64;
+  const size_t cell_bytes = gain_cell_bytes(n_ant, w32);
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(cells, (int64_t)(kPeelWsMax / cell_bytes)));
   const size_t wsbytes = (size_t)chunk * cell_bytes;
   if (mbytes > w.model_bytes || tab.size() > w.tab_n || wsbytes > w.ws_bytes) {
@@ -116,10 +118,9 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   a.comp = a.pair_bl + npairs;
   a.gains = (double2 *)gains_dev;
   a.subtract = 1;
-  // the FP64 path keeps the operator in FP64 where it fits
-  a.w32 = precision != VP_PREC_FP64;
-  a.xt = (double2 *)w.ws;
-  a.wf = (double *)((char *)w.ws + (size_t)chunk * n_ant * n_ant * sizeof(double2));
+  a.w32 = w32;
+  a.xt = w.ws;
+  a.wf = (char *)w.ws + (size_t)chunk * n_ant * n_ant * (w32 ? sizeof(float2) : sizeof(double2));
   {
     ProfScope ps(ctx, s, 3);
     for (int64_t c0 = 0; c0 < cells && e == hipSuccess; c0 += chunk) {
