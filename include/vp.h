@@ -235,8 +235,9 @@ int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes);
  * the solution moves by the tables' FP32 rounding (about 1e-7 relative).
  * gains_dev: caller-owned device memory [n_time][n_chan][n_ant] complex128
  * receiving the gains, or NULL.  data_dev as for vp_subtract.  Asynchronous
- * on hip_stream; calls on one context share a workspace of n_time x n_bl x
- * n_chan complex values and wait for the previous call to finish with it.
+ * on hip_stream; calls on one context share a workspace (n_time x n_bl x
+ * n_chan complex values, n_time x n_ant x n_chan complex128 gains and up to
+ * 1 GiB of per-cell tables) and wait for the previous call to finish with it.
  * Errors: VP_EINVAL (tiles out of range or repeated pairs, n_ant outside
  * 2..VP_PEEL_MAX_ANT, n_iter outside 0..VP_PEEL_MAX_ITER, as vp_subtract),
  * VP_ENOMEM, VP_EDEVICE. */

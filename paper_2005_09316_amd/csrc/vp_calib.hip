@@ -312,6 +312,7 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
     const double floor2 = kGainFloor * kGainFloor * s0.y;
     double rr = s0.x, rz = block_sum2<NT>(res.x * z.x + res.y * z.y, 0.0, red).x;
     const double rr0 = rr;
+    int steps = 0;  // workgroup-uniform: every stopping test uses block sums
     for (int cg = 0; cg < a.max_cg; ++cg) {
       if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2) || !(rz > 0.0)) break;
       if (own) y[k] = cmul(gk, cconj(pdir));
@@ -342,27 +343,44 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
       pdir = make_double2(z.x + beta * pdir.x, z.y + beta * pdir.y);
       rr = s1.x;
       rz = s1.y;
+      ++steps;
     }
     x = gauge_project(x, gk, k, ck, own, n, comp, g, pv);
     gk.x += x.x;
     gk.y += x.y;
     if (own) g[k] = gk;
     __syncthreads();
+    // no step taken: the gains did not change, so every further iteration
+    // would repeat this one exactly
+    if (steps == 0) break;
   }
 
-  if (a.gains && own) a.gains[(int64_t)cell * n + k] = gk;
-  if (a.subtract) {
-    const int64_t base = (int64_t)t * a.B * a.K + kc;  // element (t, b, kc) at base + b K
-    for (int b = tid; b < a.B; b += NT) {
-      const int64_t i = base + (int64_t)b * a.K;
-      const double2 m = load_vis(a.model, a.c64, i);
-      const double2 v = load_vis(a.data, a.c64, i);
-      const double2 mdl = cmul(cmul(g[a.ant1[b]], cconj(g[a.ant2[b]])), m);
-      if (a.c64)
-        ((float2 *)a.data)[i] = make_float2((float)(v.x - mdl.x), (float)(v.y - mdl.y));
-      else
-        ((double2 *)a.data)[i] = make_double2(v.x - mdl.x, v.y - mdl.y);
-    }
+  if (own) {
+    if (a.gains) a.gains[(int64_t)cell * n + k] = gk;
+    a.gw[((int64_t)t * n + k) * a.K + kc] = gk;
+  }
+}
+
+// data <- data - g_ant1 g_ant2^* I over the whole [T][B][K] array, one
+// visibility per thread (adjacent threads on adjacent channels: coalesced),
+// with the gains of cell (t, kc) from the [T][n][K] table the solve wrote
+// (adjacent channels adjacent there too).
+__global__ __launch_bounds__(256) void k_gain_subtract(GainArgs a) {
+  const int64_t total = (int64_t)a.T * a.B * a.K;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int kc = (int)(i % a.K);
+    const int64_t tb = i / a.K;
+    const int b = (int)(tb % a.B), t = (int)(tb / a.B);
+    const double2 g1 = a.gw[((int64_t)t * a.n_ant + a.ant1[b]) * a.K + kc];
+    const double2 g2 = a.gw[((int64_t)t * a.n_ant + a.ant2[b]) * a.K + kc];
+    const double2 m = load_vis(a.model, a.c64, i);
+    const double2 v = load_vis(a.data, a.c64, i);
+    const double2 mdl = cmul(cmul(g1, cconj(g2)), m);
+    if (a.c64)
+      ((float2 *)a.data)[i] = make_float2((float)(v.x - mdl.x), (float)(v.y - mdl.y));
+    else
+      ((double2 *)a.data)[i] = make_double2(v.x - mdl.x, v.y - mdl.y);
   }
 }
 
@@ -392,6 +410,14 @@ static hipError_t launch_tables(const GainArgs &a, hipStream_t s) {
 
 bool gain_supported(int n_ant) {
   return n_ant >= 2 && n_ant <= kPeelMaxAnt && gain_smem_bytes(n_ant, false, 1024) <= kPeelSmemMax;
+}
+
+hipError_t launch_gain_subtract(const GainArgs &a, hipStream_t s) {
+  const int64_t total = (int64_t)a.T * a.B * a.K;
+  if (total <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_gain_subtract, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 size_t gain_cell_bytes(int n_ant, bool w32) {

@@ -177,7 +177,7 @@ struct GainArgs {
   const int32_t *pair_bl;      // [n_ant (n_ant - 1) / 2] baseline of tile pair (i < j), -1 if none
   const int32_t *comp;         // [n_ant] connected component of each tile in the baseline graph, -1 if idle
   double2 *gains;         // [T][K][n_ant] output, or null
-  int subtract;
+  double2 *gw;            // [T][n_ant][K] gains of every cell (workspace, read by the subtract pass)
   int cell0, ncell;       // the launch covers cells cell0 .. cell0 + ncell - 1 (cell = t K + k)
   void *xt;               // workspace [ncell][n_ant][n_ant] complex X (float2 when w32, else double2)
   void *wf;               // workspace [ncell][n_ant][n_ant] |I|^2 (float when w32, else double)
@@ -195,6 +195,7 @@ hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks,
                         hipStream_t s);
 hipError_t serve_grid(int *grid);
 hipError_t launch_gain(const GainArgs &a, hipStream_t s);
+hipError_t launch_gain_subtract(const GainArgs &a, hipStream_t s);
 bool gain_supported(int n_ant);
 size_t gain_smem_bytes(int n_ant, bool w64, int threads);
 size_t gain_cell_bytes(int n_ant, bool w32);  // workspace bytes per cell

@@ -25,8 +25,8 @@ struct DeviceMem {
   void release();
 };
 
-// Device workspace of vp_peel: the model visibilities and the baseline
-// tables.  Calls on one context take turns on it (mu, and the event of the
+// Device workspace of vp_peel: the model visibilities, the baseline tables,
+// the per-cell tables of the gain solve and the gains of every cell.  Calls on one context take turns on it (mu, and the event of the
 // previous call's last kernel).
 struct PeelWork {
   std::mutex mu;
@@ -37,6 +37,8 @@ struct PeelWork {
   size_t tab_n = 0;
   void *ws = nullptr;      // per-cell tables of the gain solve
   size_t ws_bytes = 0;
+  void *gw = nullptr;      // gains of every cell, [T][n_ant][K] complex128
+  size_t gw_bytes = 0;
   hipEvent_t done = nullptr;
 };
 

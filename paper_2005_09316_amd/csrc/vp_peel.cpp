@@ -78,21 +78,24 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   const size_t cell_bytes = gain_cell_bytes(n_ant, w32);
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(cells, (int64_t)(kPeelWsMax / cell_bytes)));
   const size_t wsbytes = (size_t)chunk * cell_bytes;
-  if (mbytes > w.model_bytes || tab.size() > w.tab_n || wsbytes > w.ws_bytes) {
+  const size_t gwbytes = (size_t)cells * n_ant * sizeof(double2);
+  if (mbytes > w.model_bytes || tab.size() > w.tab_n || wsbytes > w.ws_bytes || gwbytes > w.gw_bytes) {
     w.mem.release();
-    w.model = w.ws = nullptr;
+    w.model = w.ws = w.gw = nullptr;
     w.tab = nullptr;
     w.model_bytes = std::max(mbytes, w.model_bytes);
     w.tab_n = std::max(tab.size(), w.tab_n);
     w.ws_bytes = std::max(wsbytes, w.ws_bytes);
+    w.gw_bytes = std::max(gwbytes, w.gw_bytes);
     e = w.mem.alloc(&w.model, w.model_bytes);
     if (e == hipSuccess) e = w.mem.alloc((void **)&w.tab, sizeof(int32_t) * w.tab_n);
     if (e == hipSuccess) e = w.mem.alloc(&w.ws, w.ws_bytes);
+    if (e == hipSuccess) e = w.mem.alloc(&w.gw, w.gw_bytes);
     if (e != hipSuccess) {
       w.mem.release();
-      w.model = w.ws = nullptr;
+      w.model = w.ws = w.gw = nullptr;
       w.tab = nullptr;
-      w.model_bytes = w.tab_n = w.ws_bytes = 0;
+      w.model_bytes = w.tab_n = w.ws_bytes = w.gw_bytes = 0;
       return hip_error(e, "allocating the peel workspace");
     }
   }
@@ -117,7 +120,7 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   a.pair_bl = w.tab + 2 * (size_t)B;
   a.comp = a.pair_bl + npairs;
   a.gains = (double2 *)gains_dev;
-  a.subtract = 1;
+  a.gw = (double2 *)w.gw;
   a.w32 = w32;
   a.xt = w.ws;
   a.wf = (char *)w.ws + (size_t)chunk * n_ant * n_ant * (w32 ? sizeof(float2) : sizeof(double2));
@@ -128,6 +131,7 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
       a.ncell = (int)std::min<int64_t>(chunk, cells - c0);
       e = launch_gain(a, s);
     }
+    if (e == hipSuccess) e = launch_gain_subtract(a, s);
   }
   if (e != hipSuccess) return hip_error(e, "launching the gain solve");
   if (!w.done) e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming);
