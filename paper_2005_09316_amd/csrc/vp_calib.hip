@@ -216,9 +216,10 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   const bool row = k < n;                         // sums for tile k
   const bool own = row && pt == 0;                // holds tile k's state
   const int kr = row ? k : n - 1;                 // a valid row for the others (their sums are unused)
-  // W indices of (kr, o0): lower part (o < kr) and upper part (o >= kr)
-  const int pl0 = packed_index(n, o0 < kr ? o0 : 0, kr);
-  const int ph0 = packed_index(n, kr, o0 > kr ? o0 : kr);
+  // packed position of W_{kr,o}: L(o) + kr in the lower part (o < kr), with
+  // the wave-uniform L(o) = o n - o (o + 1) / 2, and U + o in the upper part
+  const int L0 = o0 * n - o0 * (o0 + 1) / 2;
+  const int U = kr * n - kr * (kr + 1) / 2;
 
   const TT2 *X = (const TT2 *)a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
   const TT *Wf = (const TT *)a.wf + (int64_t)cl * n * n;    // |I|^2 [o n + k], zero for o == k
@@ -237,13 +238,11 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   // sum over the slice of W_ko v_o (v in LDS); the diagonal term is zero
   auto wdot = [&](const double2 *v, bool sq) {
     double2 acc = make_double2(0.0, 0.0);
-    int pl = pl0, ph = ph0;
+    int L = L0;
 #pragma unroll 4
     for (int o = o0; o < o1; ++o) {
-      const bool lower = o < kr;
-      const int p = lower ? pl : ph;
-      pl += lower ? n - o - 1 : 0;
-      ph += lower ? 0 : 1;
+      const int p = o < kr ? L + kr : U + o;
+      L += n - o - 1;
       const double wv = (double)W[p];
       const double2 vo = v[o];
       if (sq) {
@@ -262,7 +261,7 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
     double2 sx = make_double2(0.0, 0.0);
     double sd = 0.0, sa = 0.0;  // sa: sum of |g_o X_ko|, for the rounding level of r_k
     if (row) {
-#pragma unroll 2
+#pragma unroll 8
       for (int o = o0; o < o1; ++o) {
         const double2 go = g[o];
         const TT2 xt = X[(int64_t)o * n + k];
@@ -270,7 +269,8 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
         const double g2 = go.x * go.x + go.y * go.y;
         sx.x += go.x * x.x - go.y * x.y;
         sx.y += go.x * x.y + go.y * x.x;
-        sa += sqrt(g2 * (x.x * x.x + x.y * x.y));
+        // |g_o X_ko| sets the rounding level only: an FP32 square root will do
+        sa += (double)__builtin_amdgcn_sqrtf((float)(g2 * (x.x * x.x + x.y * x.y)));
         if constexpr (tab64) sd += g2 * Wf[(int64_t)o * n + k];
       }
     }
