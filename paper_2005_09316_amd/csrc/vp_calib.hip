@@ -184,8 +184,10 @@ __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
 }
 
 // One workgroup of NT threads per cell.  Thread (k, part) with
-// k = tid mod nk (nk = n rounded up to 64) and part = tid / nk sums over
-// the part-th slice o0 <= o < o1 of the tiles (wave-uniform); the part-0
+// k = tid mod nk (nk = n rounded up to 64) and part = tid / nk sums over a
+// wave-uniform share of the other tiles (the part-th slice o0 <= o < o1 for
+// the right-hand side, the part-th share of every 64-tile block for the W
+// products); the part-0
 // thread of tile k holds the tile's gain and its conjugate-gradient state.
 // W sits in LDS packed with its zero diagonal, as WT.  The operator of the
 // step uses these W values for its diagonal too, so that i g stays its
@@ -218,8 +220,13 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   const int kr = row ? k : n - 1;                 // a valid row for the others (their sums are unused)
   // packed position of W_{kr,o}: L(o) + kr in the lower part (o < kr), with
   // the wave-uniform L(o) = o n - o (o + 1) / 2, and U + o in the upper part
-  const int L0 = o0 * n - o0 * (o0 + 1) / 2;
   const int U = kr * n - kr * (kr + 1) / 2;
+  // the W products split every 64-tile block of o among the parts: part pt
+  // takes offsets [sa, sb) of each block, so that every wave has the same
+  // share of its own diagonal block (the only o where its lanes differ
+  // between the lower and the upper part) and the rest needs no test
+  const int wb = __builtin_amdgcn_readfirstlane(k >> 6);  // this wave's tiles: 64 wb .. 64 wb + 63
+  const int sa = pt < parts ? 64 * pt / parts : 0, sb = pt < parts ? 64 * (pt + 1) / parts : 0;
 
   const TT2 *X = (const TT2 *)a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
   const TT *Wf = (const TT *)a.wf + (int64_t)cl * n * n;    // |I|^2 [o n + k], zero for o == k
@@ -235,14 +242,10 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   }
   __syncthreads();
 
-  // sum over the slice of W_ko v_o (v in LDS); the diagonal term is zero
+  // sum over this part's o of W_ko v_o (v in LDS); the diagonal term is zero
   auto wdot = [&](const double2 *v, bool sq) {
     double2 acc = make_double2(0.0, 0.0);
-    int L = L0;
-#pragma unroll 4
-    for (int o = o0; o < o1; ++o) {
-      const int p = o < kr ? L + kr : U + o;
-      L += n - o - 1;
+    auto add = [&](int p, int o) {
       const double wv = (double)W[p];
       const double2 vo = v[o];
       if (sq) {
@@ -250,6 +253,26 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
       } else {
         acc.x += wv * vo.x;
         acc.y += wv * vo.y;
+      }
+    };
+    for (int c = 0; 64 * c < n; ++c) {
+      const int oa = min(n, 64 * c + sa), ob = min(n, 64 * c + sb);
+      int L = oa * n - oa * (oa + 1) / 2;
+      if (c < wb) {  // o < 64 wb <= k: lower part for every lane
+#pragma unroll 4
+        for (int o = oa; o < ob; ++o) {
+          add(L + kr, o);
+          L += n - o - 1;
+        }
+      } else if (c > wb) {  // o >= 64 (wb + 1) > k: upper part for every lane
+#pragma unroll 4
+        for (int o = oa; o < ob; ++o) add(U + o, o);
+      } else {
+#pragma unroll 4
+        for (int o = oa; o < ob; ++o) {
+          add(o < kr ? L + kr : U + o, o);
+          L += n - o - 1;
+        }
       }
     }
     return acc;
