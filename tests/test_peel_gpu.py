@@ -203,6 +203,24 @@ def test_peel_many_tiles_fp32_weights(ctx):
     assert er <= 1e-9
 
 
+@pytest.mark.parametrize("n_ant", [100, 150, 180, 200])
+def test_peel_mixed_path_solve_variants(ctx, n_ant):
+    """The mixed path picks its solve kernel by n_ant: three 256-thread cells
+    per CU up to 139 tiles, two 512-thread cells up to 176, FP64 weights in a
+    1024-thread cell up to 183 and FP32 weights beyond.  16 tiles carry
+    baselines; the other tiles stay idle (gains 1)."""
+    obs, peel_sky, a1, a2, _, data, M = _make(n_tiles=16, n_time=1, n_chan=3, n_ant=n_ant, seed=12)
+    data = _input_as(data, vp.VP_C64)
+    g, res = _run_peel(ctx, obs, peel_sky, a1, a2, n_ant, data, 10, vp.VP_PREC_MIXED, vp.VP_C64)
+    g_ref, res_ref = oracle.peel(data, M, a1, a2, n_ant, 10)
+    eg = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    er = _res_err(res, res_ref, obs, peel_sky)
+    _log("peel mixed n_ant %d: gains %.3e, residual / F %.3e" % (n_ant, eg, er))
+    assert np.array_equal(g[:, :, 16:], np.ones_like(g[:, :, 16:]))
+    assert eg <= GAIN_FACTOR * PRED_BAR[vp.VP_PREC_MIXED]
+    assert er <= RES_FACTOR * PRED_BAR[vp.VP_PREC_MIXED]
+
+
 def test_peel_full_size_sampled_channels(ctx):
     """Workload 4's observation (256 tiles, 32640 baselines, 1 time, 384
     channels, complex64 data): peel one N=80 shapelet with calibration on the
