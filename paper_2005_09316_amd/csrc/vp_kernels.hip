@@ -297,11 +297,13 @@ struct PgSmem {
 };
 
 // One tile: kTileRows rows x kPgChan channels starting at channel block cb.
-// UNI (mixed path, uniformly spaced channels): the phasors of channels 0, 3
-// and 6 of the tile are evaluated (FP64 phase, FP32 sincos) and the others
-// are those rotated by one channel step, e^{+-2 pi i t0 dnu/c}: 4 sincos and
-// 5 complex rotations per (row, component) instead of 8 sincos, with at most
-// one rotation between a channel and an evaluated phasor.
+// UNI (uniformly spaced channels): on the mixed path the phasors of channels
+// 0, 3 and 6 of the tile are evaluated (FP64 phase, FP32 sincos) and the
+// others are those rotated by one channel step, e^{+-2 pi i t0 dnu/c}: 4
+// sincos and 5 complex rotations per (row, component) instead of 8 sincos,
+// with at most one rotation between a channel and an evaluated phasor.  On
+// the FP64 path channel 0 and the step are evaluated and channels 1-7 are
+// reached by successive rotations.
 template <int PREC, bool UNI = false>
 __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
                                         PgSmem<typename PgTypes<PREC>::acc_t> &sm) {
@@ -380,27 +382,35 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
             Q = fmaf((float)g.x, (float)uu, fmaf((float)g.y, (float)vv, (float)g.z * (float)uv));
         }
         if (PREC == kFP64 && UNI) {
-          // the rotation scheme in FP64 (one rotation adds ~2e-16)
+          // FP64: channel 0's phasor and the channel step are evaluated,
+          // channels 1-7 follow by successive rotations (each adds ~2e-16 of
+          // the term: FP64 keeps a chain of seven far below its error bar)
           const double t0 = fma(u, p.x, fma(v, p.y, w * p.z));
           double c[KB], s[KB], cd, sd;
           turns_sincos_f64(t0 * f[0], c[0], s[0]);
-          turns_sincos_f64(t0 * fa3, c[3], s[3]);
-          turns_sincos_f64(t0 * fa6, c[6], s[6]);
           turns_sincos_f64(t0 * a.dfk, cd, sd);
-          c[1] = fma(c[0], cd, -s[0] * sd);
-          s[1] = fma(s[0], cd, c[0] * sd);
-          c[4] = fma(c[3], cd, -s[3] * sd);
-          s[4] = fma(s[3], cd, c[3] * sd);
-          c[7] = fma(c[6], cd, -s[6] * sd);
-          s[7] = fma(s[6], cd, c[6] * sd);
-          c[2] = fma(c[3], cd, s[3] * sd);
-          s[2] = fma(s[3], cd, -c[3] * sd);
-          c[5] = fma(c[6], cd, s[6] * sd);
-          s[5] = fma(s[6], cd, -c[6] * sd);
+#pragma unroll
+          for (int k = 1; k < KB; ++k) {
+            c[k] = fma(c[k - 1], cd, -s[k - 1] * sd);
+            s[k] = fma(s[k - 1], cd, c[k - 1] * sd);
+          }
+          // Gaussian envelope 2^(-Q f_k^2) on the same grid f_k = f_0 + k df:
+          // e_{k+1} = e_k r_k and r_{k+1} = r_k q, with r_0 = 2^(-Q df (2 f_0 + df))
+          // and q = 2^(-2 Q df^2) (three exponentials instead of eight)
+          double e = 1.0, r = 1.0, q = 1.0;
+          if (kind == 1) {
+            e = exp2(-(double)Q * (f[0] * f[0]));
+            r = exp2(-(double)Q * a.dfk * (2.0 * f[0] + a.dfk));
+            q = exp2(-2.0 * (double)Q * a.dfk * a.dfk);
+          }
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
             double S = (double)s_flux[jj][k];
-            if (kind == 1) S *= exp2(-(double)Q * (f[k] * f[k]));
+            if (kind == 1) {
+              S *= e;
+              e *= r;
+              r *= q;
+            }
             prt_re[k] = fma(S, c[k], (double)prt_re[k]);
             prt_im[k] = fma(S, s[k], (double)prt_im[k]);
           }
@@ -479,8 +489,10 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
       };
       // groups of kFlush components, unrolled, then the remainder
       int jg = 0;
+      // FP64 terms hold twice the registers: two at a time keep two waves per SIMD
+      constexpr int kUnroll = PREC == kFP64 ? 2 : kFlush;
       for (; jg + kFlush <= n; jg += kFlush) {
-#pragma unroll
+#pragma unroll kUnroll
         for (int jo = 0; jo < kFlush; ++jo) term(jg + jo);
         flush_partials();
       }
