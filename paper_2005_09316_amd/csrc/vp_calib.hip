@@ -98,7 +98,7 @@ struct TabPair<double> {
   typedef double2 type;
 };
 
-// Cells per workgroup of the table kernel (48 KB of LDS either way).
+// Cells per workgroup of the table kernel (at most 48 KB of LDS either way).
 template <typename TT>
 constexpr int tab_cells() {
   return sizeof(TT) == sizeof(float) ? 16 : 8;
@@ -118,9 +118,12 @@ template <typename TT>
 __global__ __launch_bounds__(256) void k_gain_tables(GainArgs a) {
   typedef typename TabPair<TT>::type TT2;
   constexpr int C = tab_cells<TT>();
-  __shared__ TT2 sx[C][kPeelMaxAnt];
-  __shared__ TT sw[C][kPeelMaxAnt];
+  // [C][n] pairs, then [C][n] magnitudes (sized for this n, so that small
+  // arrays fit more workgroups per CU)
+  extern __shared__ __align__(16) unsigned char tsm[];
   const int n = a.n_ant, o = blockIdx.y;
+  TT2 *sx = (TT2 *)tsm;
+  TT *sw = (TT *)(sx + C * n);
   const int c0 = blockIdx.x * C;
   const int nc = min(C, a.ncell - c0);
   for (int e = threadIdx.x; e < nc * n; e += 256) {
@@ -142,8 +145,8 @@ __global__ __launch_bounds__(256) void k_gain_tables(GainArgs a) {
       x.y = (TT)xv.y;
       w = (TT)(m.x * m.x + m.y * m.y);
     }
-    sx[j][k] = x;
-    sw[j][k] = w;
+    sx[j * n + k] = x;
+    sw[j * n + k] = w;
   }
   __syncthreads();
   TT2 *X = (TT2 *)a.xt;
@@ -151,8 +154,8 @@ __global__ __launch_bounds__(256) void k_gain_tables(GainArgs a) {
   for (int e = threadIdx.x; e < nc * n; e += 256) {
     const int j = e / n, k = e - j * n;
     const int64_t off = ((int64_t)(c0 + j) * n + o) * n + k;
-    X[off] = sx[j][k];
-    W[off] = sw[j][k];
+    X[off] = sx[j * n + k];
+    W[off] = sw[j * n + k];
   }
 }
 
@@ -426,7 +429,8 @@ static hipError_t launch_solve(const GainArgs &a, hipStream_t s) {
 template <typename TT>
 static hipError_t launch_tables(const GainArgs &a, hipStream_t s) {
   constexpr int C = tab_cells<TT>();
-  hipLaunchKernelGGL(k_gain_tables<TT>, dim3((unsigned)((a.ncell + C - 1) / C), (unsigned)a.n_ant), dim3(256), 0, s,
+  const size_t sm = (size_t)C * a.n_ant * (sizeof(typename TabPair<TT>::type) + sizeof(TT));
+  hipLaunchKernelGGL(k_gain_tables<TT>, dim3((unsigned)((a.ncell + C - 1) / C), (unsigned)a.n_ant), dim3(256), sm, s,
                      a);
   return hipGetLastError();
 }
