@@ -159,7 +159,10 @@ __global__ __launch_bounds__(256) void k_gain_tables(GainArgs a) {
   }
 }
 
-// Sums of two values over the workgroup (NT threads) in one pass.
+// Sums of two values over the workgroup (NT threads) in one pass, through
+// the scratch red[NT / 64].  One barrier: the caller alternates between two
+// scratch buffers, and a workgroup barrier separates the last reads of a
+// buffer from its next writes.
 template <int NT>
 __device__ __forceinline__ double2 block_sum2(double u, double v, double2 *red) {
 #pragma unroll
@@ -168,7 +171,6 @@ __device__ __forceinline__ double2 block_sum2(double u, double v, double2 *red) 
     v += __shfl_xor(v, o);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
   if (lane == 0) red[wave] = make_double2(u, v);
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
@@ -207,8 +209,9 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   double2 *pa = y + kPeelMaxAnt;                  // [NT] partial sums
   double *pv = (double *)(pa + NT);               // [kPeelMaxAnt] projection scratch
   int *comp = (int *)(pv + kPeelMaxAnt);          // [kPeelMaxAnt] connected component of each tile
-  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [NT / 64] reduction scratch
-  WT *W = (WT *)(red + NT / 64);                  // [n (n + 1) / 2] |I|^2, packed with the diagonal
+  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [2][NT / 64] reduction scratch, used alternately
+  double2 *red2 = red + NT / 64;
+  WT *W = (WT *)(red2 + NT / 64);                 // [n (n + 1) / 2] |I|^2, packed with the diagonal
 
   const int cl = blockIdx.x, cell = a.cell0 + cl;
   const int t = cell / a.K, kc = cell % a.K;
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
     double2 z = make_double2(minv * r.x, minv * r.y), pdir = z;
     const double2 s0 = block_sum2<NT>(res.x * res.x + res.y * res.y, scale * scale, red);
     const double floor2 = kGainFloor * kGainFloor * s0.y;
-    double rr = s0.x, rz = block_sum2<NT>(res.x * z.x + res.y * z.y, 0.0, red).x;
+    double rr = s0.x, rz = block_sum2<NT>(res.x * z.x + res.y * z.y, 0.0, red2).x;
     const double rr0 = rr;
     int steps = 0;  // workgroup-uniform: every stopping test uses block sums
     for (int cg = 0; cg < a.max_cg; ++cg) {
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
       res.x -= alpha * q.x;
       res.y -= alpha * q.y;
       z = make_double2(minv * res.x, minv * res.y);
-      const double2 s1 = block_sum2<NT>(res.x * res.x + res.y * res.y, res.x * z.x + res.y * z.y, red);
+      const double2 s1 = block_sum2<NT>(res.x * res.x + res.y * res.y, res.x * z.x + res.y * z.y, red2);
       const double beta = s1.y / rz;
       pdir = make_double2(z.x + beta * pdir.x, z.y + beta * pdir.y);
       rr = s1.x;
@@ -413,7 +416,7 @@ __global__ __launch_bounds__(256) void k_gain_subtract(GainArgs a) {
 size_t gain_smem_bytes(int n_ant, bool w64, int threads) {
   const size_t packed = (size_t)n_ant * (n_ant + 1) / 2;
   return kPeelMaxAnt * (2 * sizeof(double2) + sizeof(double) + sizeof(int)) + threads * sizeof(double2) +
-         (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
+         2 * (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
 }
 
 template <typename WT, int NT, typename TT>

@@ -206,7 +206,7 @@ def test_peel_many_tiles_fp32_weights(ctx):
 @pytest.mark.parametrize("n_ant", [100, 150, 180, 200])
 def test_peel_mixed_path_solve_variants(ctx, n_ant):
     """The mixed path picks its solve kernel by n_ant: three 256-thread cells
-    per CU up to 139 tiles, two 512-thread cells up to 176, FP64 weights in a
+    per CU up to 139 tiles, two 512-thread cells up to 175, FP64 weights in a
     1024-thread cell up to 183 and FP32 weights beyond.  16 tiles carry
     baselines; the other tiles stay idle (gains 1)."""
     obs, peel_sky, a1, a2, _, data, M = _make(n_tiles=16, n_time=1, n_chan=3, n_ant=n_ant, seed=12)
