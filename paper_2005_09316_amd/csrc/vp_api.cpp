@@ -302,7 +302,7 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.n_cb = obs->Kpad / kPgChan;
   a.lut = lut;
   a.dfk = obs->dfk;
-  a.uniform = obs->uniform;
+  a.uniform = precision == kFP64 || precision == kLut ? obs->uniform64 : obs->uniform;
   // A sky of shapelets only skips the point/Gaussian pass, which would only
   // write zeros (predict) or rewrite the data unchanged (subtract).
   const bool pg_pass = sky->P + sky->G > 0 || sky->S == 0;
@@ -435,13 +435,16 @@ int vp_create_obs(vp_ctx *ctx, const vp_obs_desc *desc, vp_obs **out) {
   std::vector<double> fk(o->Kpad);
   for (int k = 0; k < o->Kpad; ++k) fk[k] = desc->freq_hz[std::min(k, o->K - 1)] / kLightSpeed;
   if (o->K >= 2) {
-    // uniformly spaced channels let the mixed path rotate phasors between
-    // channels; the grid must hold to 1e-12 of nu/c (phase error below
-    // 1e-8 turns for |t0| up to 1e4 m)
+    // uniformly spaced channels let the kernels rotate phasors between
+    // channels: the mixed path while the grid holds to 1e-12 of nu/c (phase
+    // error below 1e-8 turns for |t0| up to 1e4 m), the FP64 path while it
+    // holds to 1e-15 (1e-11 turns)
     const double d = (fk[o->K - 1] - fk[0]) / (o->K - 1);
-    bool uni = d != 0.0;
-    for (int k = 0; k < o->K && uni; ++k) uni = std::fabs(fk[k] - std::fma((double)k, d, fk[0])) <= 1e-12 * std::fabs(fk[0]);
+    double dev = 0.0;
+    for (int k = 0; k < o->K; ++k) dev = std::max(dev, std::fabs(fk[k] - std::fma((double)k, d, fk[0])));
+    const bool uni = d != 0.0 && dev <= 1e-12 * std::fabs(fk[0]);
     o->uniform = uni ? 1 : 0;
+    o->uniform64 = uni && dev <= 1e-15 * std::fabs(fk[0]) ? 1 : 0;
     o->dfk = uni ? d : 0.0;
   }
   hipError_t e = upload(&o->uvw, desc->uvw_m, 3 * nrows, o->mem);

@@ -116,6 +116,7 @@ struct vp_obs {
   double *fk = nullptr;   // device [Kpad], nu/c
   double dfk = 0;         // channel step of nu/c when uniform
   int uniform = 0;        // channels uniformly spaced (to 1e-12 of nu/c)
+  int uniform64 = 0;      // ... to 1e-15 of nu/c (enough for the FP64 path)
   std::vector<double> h_freq;
   int jobs = 0;           // pending serving jobs using it (guarded by ctx->mu)
   vp::DeviceMem mem;

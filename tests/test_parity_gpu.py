@@ -53,13 +53,27 @@ def _case(name):
         # from zero (the output buffer holds NaN before a predict)
         obs, sky = synth.make_config(2, n_tiles=20, n_time=2, n_chan=6)
         return obs, synth.select_components(sky, points=[], gauss=[])
+    if name == "mwa-descending":
+        # uniformly spaced channels in decreasing frequency: a negative channel
+        # step for the phasor rotations and the FP64 envelope recurrence
+        freqs = np.linspace(190e6, 170e6, 11)
+        return synth.make_config(1, n_tiles=20, n_time=2, n_chan=11, n_point=200, n_gauss=40,
+                                 shapelet_nmax=[20], freq_hz=freqs)
+    if name == "mwa-jittered":
+        # a grid uniform to 1e-13 of nu: the mixed path rotates phasors, the
+        # FP64 path (which rotates only on grids uniform to 1e-15) does not
+        rng = np.random.default_rng(32)
+        freqs = np.linspace(170e6, 190e6, 11) * (1.0 + 1e-13 * rng.uniform(-1.0, 1.0, 11))
+        return synth.make_config(1, n_tiles=20, n_time=2, n_chan=11, n_point=200, n_gauss=40,
+                                 shapelet_nmax=[20], freq_hz=freqs)
     if name == "nmax-limit":
         return synth.make_config(0, n_tiles=16, n_time=2, n_chan=5, n_point=3, n_gauss=2,
                                  shapelet_nmax=[96, 0, 1, 31, 32, 63, 64])
     raise KeyError(name)
 
 
-CASES = ["tiny", "mwa-mid", "fornax-mid", "lobes-only", "mwa-nonuniform", "nmax-limit"]
+CASES = ["tiny", "mwa-mid", "fornax-mid", "lobes-only", "mwa-nonuniform", "mwa-descending", "mwa-jittered",
+         "nmax-limit"]
 _REF = {}
 
 
