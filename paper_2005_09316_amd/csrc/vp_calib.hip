@@ -192,9 +192,9 @@ __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
 // k = tid mod nk (nk = n rounded up to 64) and part = tid / nk sums over a
 // wave-uniform share of the other tiles (the part-th slice o0 <= o < o1 for
 // the right-hand side, the part-th share of every 64-tile block for the W
-// products); the part-0
-// thread of tile k holds the tile's gain and its conjugate-gradient state.
-// W sits in LDS packed with its zero diagonal, as WT.  The operator of the
+// products); the part-0 thread of tile k holds the tile's gain and its
+// conjugate-gradient state; threads with part >= NT / nk (when nk does not
+// divide NT) take no share.  W sits in LDS packed with its zero diagonal, as WT.  The operator of the
 // step uses these W values for its diagonal too, so that i g stays its
 // exact null vector; the right-hand side uses the tables (TT), and with
 // FP32 tables that same LDS copy of W for D.  The solve is conjugate
