@@ -1034,53 +1034,73 @@ __device__ __forceinline__ double lut_at(const LutPos &q, int n) {
 }
 
 template <bool LUT>
-__global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
+__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(3))) void k_shp_fp64(TileArgs a) {
   constexpr int KB = kShpChan;
+  // one 32-column chunk of the signed coefficient matrix (rows 0 .. N - m0),
+  // staged in LDS for the whole workgroup and read as broadcasts: from
+  // global memory every row dot waited on its wave-uniform loads
+  __shared__ double sC[(kNmaxLimit + 1) * 32];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int cb = tile / a.n_rb, rb = tile % a.n_rb;
   const int k0 = cb * KB;
+  const int nc = min(KB, a.K - k0);  // channels of this tile
   const int tid = threadIdx.x;
   const int64_t row = (int64_t)rb * kTileRows + tid;
   const bool valid = row < a.nrows;
   const int64_t rowc = valid ? row : a.nrows - 1;
   const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
 
-  for (int c = 0; c < KB; ++c) {
-    if (k0 + c >= a.K) break;
-    const double f = a.fk[k0 + c];
-    double acc_re = 0.0, acc_im = 0.0;
-    for (int j = 0; j < a.S; ++j) {
-      const int N = a.t.nmax[j];
-      const double *fr = a.d.sframe + 12 * j;
-      const double xa = f * fma(fr[0], u, fma(fr[1], v, fr[2] * w));
-      const double xb = f * fma(fr[3], u, fma(fr[4], v, fr[5] * w));
-      const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
-      // The second axis in chunks of 32 orders (its recurrence carried
-      // across chunks); per chunk the first axis is walked from order 0 and
-      // each row n1 is dotted with the chunk's part of row n1 of the signed
-      // coefficient matrix.  32 values per lane stay in registers.
-      const double *C = a.t.c64 + a.t.c64_off[j];
-      const int ld = a.t.c64_ld[j];
-      const double sxa = 1.41421356237309504880 * xa, sxb = 1.41421356237309504880 * xb;
-      LutPos qa, qb;
-      if constexpr (LUT) {
-        qa = lut_pos(a.lut, xa);
-        qb = lut_pos(a.lut, xb);
+  double acc_re[KB], acc_im[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) acc_re[c] = acc_im[c] = 0.0;
+  for (int j = 0; j < a.S; ++j) {
+    const int N = a.t.nmax[j];
+    const double *fr = a.d.sframe + 12 * j;
+    const double am = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
+    const double bm = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
+    const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
+    // The second axis in chunks of 32 orders (its recurrence carried across
+    // chunks, per channel); per chunk and channel the first axis is walked
+    // from order 0 and each row n1 is dotted with the chunk's part of row n1
+    // of the signed coefficient matrix.  32 values per lane stay in registers.
+    const double *C = a.t.c64 + a.t.c64_off[j];
+    const int ld = a.t.c64_ld[j];
+    double bn[KB], bm1[KB], xr[KB], xi[KB];  // per channel: second-axis recurrence, sums
+#pragma unroll
+    for (int c = 0; c < KB; ++c) {
+      const double xb = a.fk[k0 + c] * bm;
+      bn[c] = kPiM14 * exp(-0.5 * xb * xb);
+      bm1[c] = xr[c] = xi[c] = 0.0;
+    }
+    for (int ch = 0; 32 * ch <= N; ++ch) {
+      const int m0 = 32 * ch;
+      __syncthreads();  // the previous chunk is no longer read
+      for (int i = tid; i < (N - m0 + 1) * 32; i += kTileRows) {
+        const int col = m0 + (i & 31);
+        sC[i] = col < ld ? C[(int64_t)(i >> 5) * ld + col] : 0.0;
       }
-      double bn = kPiM14 * exp(-0.5 * xb * xb), bm1 = 0.0;  // second-axis recurrence state
-      double xr = 0.0, xi = 0.0;
-      for (int ch = 0; 32 * ch <= N; ++ch) {
-        const int m0 = 32 * ch;
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < KB; ++c) {
+        if (c >= nc) break;
+        const double f = a.fk[k0 + c];
+        const double xa = f * am, xb = f * bm;
+        const double sxa = 1.41421356237309504880 * xa, sxb = 1.41421356237309504880 * xb;
+        LutPos qa, qb;
+        if constexpr (LUT) {
+          qa = lut_pos(a.lut, xa);
+          qb = lut_pos(a.lut, xb);
+        }
         double pb[32];
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
           if constexpr (LUT) {
             pb[i] = m0 + i <= kNmaxLimit ? lut_at(qb, m0 + i) : 0.0;
           } else {
-            pb[i] = bn;
-            const double nx = herm_step<double>(sxb, bn, bm1, m0 + i);  // orders <= 127: table size
-            bm1 = bn;
-            bn = nx;
+            pb[i] = bn[c];
+            const double nx = herm_step<double>(sxb, bn[c], bm1[c], m0 + i);  // orders <= 127: table size
+            bm1[c] = bn[c];
+            bn[c] = nx;
           }
         }
         double pa, pam1 = 0.0;
@@ -1089,7 +1109,7 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
         else
           pa = kPiM14 * exp(-0.5 * xa * xa);
         for (int n1 = 0; n1 <= N - m0; ++n1) {
-          const double *Cr = C + (int64_t)n1 * ld + m0;
+          const double *Cr = sC + n1 * 32;
           double te = 0.0, to = 0.0;
 #pragma unroll
           for (int b8 = 0; b8 < 4; ++b8) {
@@ -1102,11 +1122,11 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
             }
           }
           if (n1 & 1) {
-            xr = fma(pa, to, xr);
-            xi = fma(pa, te, xi);
+            xr[c] = fma(pa, to, xr[c]);
+            xi[c] = fma(pa, te, xi[c]);
           } else {
-            xr = fma(pa, te, xr);
-            xi = fma(pa, to, xi);
+            xr[c] = fma(pa, te, xr[c]);
+            xi[c] = fma(pa, to, xi[c]);
           }
           if constexpr (LUT) {
             pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
@@ -1117,41 +1137,49 @@ __global__ __launch_bounds__(kTileRows) void k_shp_fp64(TileArgs a) {
           }
         }
       }
+    }
+#pragma unroll
+    for (int c = 0; c < KB; ++c) {
+      if (c >= nc) break;
+      const double f = a.fk[k0 + c];
       double cs, sn;
       turns_sincos_f64(t0 * f, cs, sn);
       const double S = a.d.flux64[(int64_t)(a.P + a.G + j) * a.Kpad + k0 + c];
-      acc_re += S * (xr * cs - xi * sn);
-      acc_im += S * (xr * sn + xi * cs);
+      acc_re[c] += S * (xr[c] * cs - xi[c] * sn);
+      acc_im[c] += S * (xr[c] * sn + xi[c] * cs);
     }
-    if (valid) {
-      const int64_t idx = row * a.K + k0 + c;
-      double2 *o = (double2 *)a.vis;
-      float2 *o32 = (float2 *)a.vis;
-      double xr = 0.0, xi = 0.0;
-      if (a.fresh) {
-        // no point/Gaussian pass wrote this visibility
-      } else if (a.c64) {
-        const float2 x = o32[idx];
-        xr = x.x;
-        xi = a.conj ? -x.y : x.y;
-      } else {
-        const double2 x = o[idx];
-        xr = x.x;
-        xi = a.conj ? -x.y : x.y;
-      }
-      if (a.subtract) {
-        xr -= acc_re;
-        xi -= acc_im;
-      } else {
-        xr += acc_re;
-        xi += acc_im;
-      }
-      if (a.conj) xi = -xi;
-      if (a.c64)
-        o32[idx] = make_float2((float)xr, (float)xi);
-      else
-        o[idx] = make_double2(xr, xi);
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    if (c >= nc) break;
+    const int64_t idx = row * a.K + k0 + c;
+    double2 *o = (double2 *)a.vis;
+    float2 *o32 = (float2 *)a.vis;
+    double xr = 0.0, xi = 0.0;
+    if (a.fresh) {
+      // no point/Gaussian pass wrote this visibility
+    } else if (a.c64) {
+      const float2 x = o32[idx];
+      xr = x.x;
+      xi = a.conj ? -x.y : x.y;
+    } else {
+      const double2 x = o[idx];
+      xr = x.x;
+      xi = a.conj ? -x.y : x.y;
     }
+    if (a.subtract) {
+      xr -= acc_re[c];
+      xi -= acc_im[c];
+    } else {
+      xr += acc_re[c];
+      xi += acc_im[c];
+    }
+    if (a.conj) xi = -xi;
+    if (a.c64)
+      o32[idx] = make_float2((float)xr, (float)xi);
+    else
+      o[idx] = make_double2(xr, xi);
   }
 }
 
