@@ -222,7 +222,9 @@ int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes);
  * of Sec. 5.1, starting from unit gains, each step the minimum-norm
  * least-squares solution (the data leave one global phase free per
  * connected group of tiles; a step stops early once the right-hand side is
- * at FP64 rounding level) -- and subtract: data <- data - g_ant1 g_ant2^* I.
+ * at FP64 rounding level, and a cell whose step is then zero has converged
+ * and takes no further iterations) -- and subtract: data <- data - g_ant1
+ * g_ant2^* I.
  * ant1, ant2: host arrays [n_bl] (n_bl of obs), the tiles (0..n_ant-1,
  * distinct, each pair at most once) of each baseline, the same for every
  * time step; read during the call only.
