@@ -570,6 +570,7 @@ def main():
     ap.add_argument("--only-paper-peel", action="store_true", help="run the paper-scale calibrated peel alone")
     ap.add_argument("--only-shapelets", action="store_true",
                     help="run only the shapelet-contraction leg and print its JSON")
+    ap.add_argument("--only-serve", action="store_true", help="run the serving stream alone and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (its HBM counters scale the kernels')")
     args = ap.parse_args()
@@ -591,6 +592,10 @@ def main():
         return
     if args.only_paper_peel:
         print(json.dumps(paper_peel()), flush=True)
+        return
+    if args.only_serve:
+        print(json.dumps(serve_stream(args.serve_requests, args.serve_rate, int(args.serve_budget_gb * 1e9))),
+              flush=True)
         return
 
     t_gen = time.time()
