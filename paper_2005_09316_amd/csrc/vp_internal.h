@@ -16,6 +16,7 @@ constexpr int kPgChan = 8;     // channels per point/Gaussian tile (per thread)
 constexpr int kShpChan = 4;    // channels per shapelet tile
 constexpr int kChunk = 64;     // components staged in LDS at a time
 constexpr int kFlush = 8;      // components summed plainly before a Kahan step
+constexpr int kFlushMixed = 16; // mixed path: components per FP64 add (two kFlush partials, summed in FP32)
 constexpr int kNmaxLimit = 96; // largest n1 + n2
 constexpr int kMBMax = 4;      // 32-row blocks of the n1 axis: ceil(97 / 32)
 

@@ -15,8 +15,9 @@
 //               unit (input in turns); with uniformly spaced channels the
 //               mixed path evaluates 3 of every 8 channels and the channel
 //               step and rotates the other phasors.  Sums are plain FP32
-//               over kFlush components, then added into FP64 sums (the
-//               FP32-only path: Kahan-compensated FP32 sums).
+//               over kFlush components; the mixed path adds two such
+//               partials in FP32 and then into FP64 sums (the FP32-only
+//               path: Kahan-compensated FP32 sums).
 //   k_shp_mfma  shapelets.  Per (visibility, shapelet): rotate uvw into the
 //               shapelet's frame, walk the rescaled Hermite recurrence for
 //               both axes (FP64: it costs the same issue slots as FP32 on this
@@ -326,14 +327,16 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
   for (int k = 0; k < KB; ++k) f[k] = a.fk[k0 + k];
 
   // Partial sums over kFlush components in acc_t; across them, the mixed
-  // path adds the partials into FP64 sums (FP64 adds issue at the FP32 rate
-  // here, and two operations per value replace Kahan's four), the FP32-only
-  // path keeps Kahan-compensated FP32 sums, the FP64 path plain FP64 sums.
-  acc_t sum_re[KB], sum_im[KB], cmp_re[KB], cmp_im[KB], prt_re[KB], prt_im[KB];
+  // path adds each pair of partials in FP32 (hld + prt; the pair's rounding
+  // error stays within kFlush units of roundoff of its terms' magnitude) and
+  // that into FP64 sums (FP64 adds issue at the FP32 rate here, and three
+  // operations per value and pair replace Kahan's eight), the FP32-only path
+  // keeps Kahan-compensated FP32 sums, the FP64 path plain FP64 sums.
+  acc_t sum_re[KB], sum_im[KB], cmp_re[KB], cmp_im[KB], prt_re[KB], prt_im[KB], hld_re[KB], hld_im[KB];
   double dsum_re[KB], dsum_im[KB];
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    sum_re[k] = sum_im[k] = cmp_re[k] = cmp_im[k] = prt_re[k] = prt_im[k] = 0;
+    sum_re[k] = sum_im[k] = cmp_re[k] = cmp_im[k] = prt_re[k] = prt_im[k] = hld_re[k] = hld_im[k] = 0;
     dsum_re[k] = dsum_im[k] = 0.0;
   }
 
@@ -474,12 +477,23 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
           }
         }
       };
+      // mixed path: a group's first kFlush terms are held aside and added to
+      // the second kFlush terms' partial in FP32 before the FP64 add
+      auto hold_partials = [&]() {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          hld_re[k] = prt_re[k];
+          hld_im[k] = prt_im[k];
+          prt_re[k] = prt_im[k] = 0;
+        }
+      };
       auto flush_partials = [&]() {
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
           if constexpr (PREC == kMixed) {
-            dsum_re[k] += (double)prt_re[k];
-            dsum_im[k] += (double)prt_im[k];
+            dsum_re[k] += (double)(prt_re[k] + hld_re[k]);
+            dsum_im[k] += (double)(prt_im[k] + hld_im[k]);
+            hld_re[k] = hld_im[k] = 0;
           } else {
             kahan_add(sum_re[k], cmp_re[k], prt_re[k]);
             kahan_add(sum_im[k], cmp_im[k], prt_im[k]);
@@ -487,17 +501,24 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
           prt_re[k] = prt_im[k] = 0;
         }
       };
-      // groups of kFlush components, unrolled, then the remainder
+      // groups of kGroup components, unrolled, then the remainder
+      constexpr int kGroup = PREC == kMixed ? kFlushMixed : kFlush;
       int jg = 0;
       // FP64 terms hold twice the registers: two at a time keep two waves per SIMD
-      constexpr int kUnroll = PREC == kFP64 ? 2 : kFlush;
-      for (; jg + kFlush <= n; jg += kFlush) {
+      constexpr int kUnroll = PREC == kFP64 ? 2 : kGroup;
+      for (; jg + kGroup <= n; jg += kGroup) {
 #pragma unroll kUnroll
-        for (int jo = 0; jo < kFlush; ++jo) term(jg + jo);
+        for (int jo = 0; jo < kGroup; ++jo) {
+          if (kGroup > kFlush && jo == kFlush) hold_partials();
+          term(jg + jo);
+        }
         flush_partials();
       }
       if (jg < n) {
-        for (int jj = jg; jj < n; ++jj) term(jj);
+        for (int jj = jg; jj < n; ++jj) {
+          if (kGroup > kFlush && jj - jg == kFlush) hold_partials();
+          term(jj);
+        }
         flush_partials();
       }
     }
