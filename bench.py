@@ -74,7 +74,7 @@ SLOTS_POINT, SLOTS_GAUSS, SLOTS_ROW_COMP = 7, 10, 3
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (summary in
 # profiles/k_pg_tile_mwa-like_hbm-traffic.md), valid for the kernel source
 # whose hash is recorded; reported as null once that source changes.
-PG_TRAFFIC = {"bytes": 128.0e6 + 29.1e6, "source_sha256_16": "d013c959dbff6a82"}
+PG_TRAFFIC = {"bytes": 128.0e6 + 29.1e6, "source_sha256_16": "ce22dd23a7358942"}
 
 
 # dense MFMA peaks and the FP64 vector peak (TFLOP/s)

@@ -331,7 +331,8 @@ __device__ __forceinline__ void pg_tile(const TileArgs &a, int rb, int cb,
   // error stays within kFlush units of roundoff of its terms' magnitude) and
   // that into FP64 sums (FP64 adds issue at the FP32 rate here, and three
   // operations per value and pair replace Kahan's eight), the FP32-only path
-  // keeps Kahan-compensated FP32 sums, the FP64 path plain FP64 sums.
+  // keeps Kahan-compensated FP32 sums and the FP64 path Kahan-compensated
+  // FP64 sums of its FP64 partials.
   acc_t sum_re[KB], sum_im[KB], cmp_re[KB], cmp_im[KB], prt_re[KB], prt_im[KB], hld_re[KB], hld_im[KB];
   double dsum_re[KB], dsum_im[KB];
 #pragma unroll
