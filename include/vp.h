@@ -193,7 +193,11 @@ typedef struct {
 
 typedef struct {
   int32_t status;   /* VP_OK or the job's error code */
-  uint64_t t_submit, t_admit, t_start, t_done; /* CLOCK_MONOTONIC ns */
+  uint64_t t_submit, t_admit, t_start, t_done; /* CLOCK_MONOTONIC ns, as the scheduler thread saw them */
+  /* device wall clock (ticks of hipDeviceAttributeWallClockRate, one clock per
+   * device) when the job's first tile started and when its last tile ended;
+   * comparable between jobs of one context; 0 for a job that ran no tile */
+  uint64_t dev_first_tile, dev_last_tile;
 } vp_job_result;
 
 /* Enqueue a job; returns a ticket.  The caller's writes to job->vis_dev (the

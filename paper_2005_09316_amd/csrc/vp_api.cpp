@@ -135,6 +135,7 @@ int get_derived(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, hipStream_t s
         hipError_t e = hipStreamWaitEvent(stream, d->ready, 0);
         if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
       }
+      d->serve_built = false;  // a direct call's kernels may read it from now on: never evicted by serving
       *out = d;
       return VP_OK;
     }
@@ -168,6 +169,7 @@ int serve_derived(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, DerivedEntr
   const auto key = std::make_pair(sky->id, obs->id);
   auto it = ctx->derived.find(key);
   if (it != ctx->derived.end()) {
+    it->second->serve_users += 1;
     *out = it->second;
     *build = false;
     return VP_OK;
@@ -176,6 +178,8 @@ int serve_derived(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, DerivedEntr
   int rc = alloc_derived(sky, obs, &d);
   if (rc != VP_OK) return rc;
   d->building = true;
+  d->serve_built = true;
+  d->serve_users = 1;
   ctx->derived[key] = d;
   ctx->lib_bytes += d->mem.total;
   *out = d;
@@ -192,6 +196,54 @@ bool derived_ready(vp_ctx *ctx, DerivedEntry *d) {
 void derived_built(vp_ctx *ctx, DerivedEntry *d) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   d->building = false;
+}
+
+static void free_entry(vp_ctx *ctx, DerivedEntry *d) {
+  // caller holds ctx->mu and has removed d from ctx->derived
+  if (d->ready) {
+    (void)hipEventSynchronize(d->ready);
+    (void)hipEventDestroy(d->ready);
+  }
+  ctx->lib_bytes -= d->mem.total;
+  d->mem.release();
+  delete d;
+}
+
+void serve_release_derived(vp_ctx *ctx, DerivedEntry *d) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  d->serve_users -= 1;
+}
+
+void serve_abandon_derived(vp_ctx *ctx, DerivedEntry *d) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  d->serve_users -= 1;
+  for (auto it = ctx->derived.begin(); it != ctx->derived.end(); ++it)
+    if (it->second == d) {
+      ctx->derived.erase(it);
+      free_entry(ctx, d);
+      return;
+    }
+}
+
+uint64_t serve_evictable_bytes(vp_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  uint64_t b = 0;
+  for (auto &kv : ctx->derived)
+    if (kv.second->serve_built && kv.second->serve_users == 0 && !kv.second->building) b += kv.second->mem.total;
+  return b;
+}
+
+void serve_evict(vp_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (auto it = ctx->derived.begin(); it != ctx->derived.end();) {
+    DerivedEntry *d = it->second;
+    if (d->serve_built && d->serve_users == 0 && !d->building) {
+      it = ctx->derived.erase(it);
+      free_entry(ctx, d);
+    } else {
+      ++it;
+    }
+  }
 }
 
 void drop_derived(vp_ctx *ctx, uint64_t sky_id, uint64_t obs_id) {
@@ -275,16 +327,11 @@ static int get_lut(vp_ctx *ctx, hipStream_t stream, const float **out) {
   return VP_OK;
 }
 
-int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis,
-              int subtract, hipStream_t stream) {
-  DerivedEntry *d = nullptr;
-  int rc = get_derived(ctx, sky, obs, stream, &d);
-  if (rc != VP_OK) return rc;
-  const float *lut = nullptr;
-  if (precision == kLut && sky->S > 0) {
-    rc = get_lut(ctx, stream, &lut);
-    if (rc != VP_OK) return rc;
-  }
+// Launch the point/Gaussian and shapelet passes over the visibility tiles
+// with the pair's tables `d`.  prof: the context whose profiling records the
+// launches, or null.
+static int launch_passes(vp_ctx *prof, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis,
+                         int subtract, hipStream_t stream, const Derived &d, const float *lut) {
   TileArgs a;
   a.nrows = (int64_t)obs->T * obs->B;
   a.K = obs->K;
@@ -292,7 +339,7 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.uvw = obs->uvw;
   a.fk = obs->fk;
   a.P = sky->P; a.G = sky->G; a.S = sky->S;
-  a.d = d->d;
+  a.d = d;
   a.t = sky->tiles;
   a.vis = vis;
   a.subtract = subtract;
@@ -309,18 +356,31 @@ int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, 
   a.fresh = !pg_pass && !subtract;
   hipError_t e = hipSuccess;
   if (pg_pass) {
-    ProfScope ps(ctx, stream, 1);
+    ProfScope ps(prof, stream, 1);
     e = launch_pg(a, precision, stream);
   }
   if (e != hipSuccess) return hip_error(e, "launching the point/Gaussian kernel");
   if (sky->S > 0) {
     a.n_cb = (obs->K + kShpChan - 1) / kShpChan;
-    ProfScope ps(ctx, stream, 2);
+    ProfScope ps(prof, stream, 2);
     e = launch_shp(a, precision, sky->max_nmax, stream);
     if (e == hipErrorNotSupported) return set_error(VP_EINVAL, "precision %d has no shapelet kernel", precision);
     if (e != hipSuccess) return hip_error(e, "launching the shapelet kernel");
   }
   return VP_OK;
+}
+
+int run_tiles(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis,
+              int subtract, hipStream_t stream) {
+  DerivedEntry *d = nullptr;
+  int rc = get_derived(ctx, sky, obs, stream, &d);
+  if (rc != VP_OK) return rc;
+  const float *lut = nullptr;
+  if (precision == kLut && sky->S > 0) {
+    rc = get_lut(ctx, stream, &lut);
+    if (rc != VP_OK) return rc;
+  }
+  return launch_passes(ctx, sky, obs, precision, dtype, vis, subtract, stream, d->d, lut);
 }
 
 int check_call(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis) {
@@ -351,6 +411,8 @@ int vp_create_ctx(int hip_device, uint64_t hbm_budget_bytes, vp_ctx **out) {
   if (hip_device < 0 || hip_device >= n) return set_error(VP_EINVAL, "device %d out of range (%d devices)", hip_device, n);
   DeviceGuard g(hip_device);
   if (!g.ok) return set_error(VP_EDEVICE, "cannot select device %d", hip_device);
+  e = device_init(hip_device);
+  if (e != hipSuccess) return hip_error(e, "initialising the device");
   size_t free_b = 0, total_b = 0;
   e = hipMemGetInfo(&free_b, &total_b);
   if (e != hipSuccess) return hip_error(e, "hipMemGetInfo");

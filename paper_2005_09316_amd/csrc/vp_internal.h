@@ -146,6 +146,8 @@ struct ServeHost {       // host-mapped, coherent
   uint64_t stop;         // non-zero: workers exit once idle
   uint64_t started[kServeSlots];   // seq of the job whose first tile has started
   uint64_t finished[kServeSlots];  // seq of the job whose last tile has finished
+  uint64_t started_clk[kServeSlots];   // device wall clock when that first tile started
+  uint64_t finished_clk[kServeSlots];  // device wall clock when that last tile finished
   uint64_t tabled[kServeSlots];    // seq_table of the job whose tables are built
   uint64_t ring[kRingSize];        // (slot << 48) | (table item << 47) | item index
   ServeJobDesc jobs[kServeSlots];
@@ -184,6 +186,11 @@ struct GainArgs {
   void *wf;               // workspace [ncell][n_ant][n_ant] |I|^2 (float when w32, else double)
   int w32;                // 1 (mixed path): FP32 tables and FP32 W in the step's operator, FP64 sums
 };
+
+// Device set-up (vp_kernels.hip): the recurrence constants, once per device
+// and process (the device must be current).
+constexpr int kMaxDevices = 64;
+hipError_t device_init(int dev);
 
 // Host-side launchers (vp_kernels.hip).
 hipError_t launch_derive(const DeriveArgs &a, hipStream_t s);

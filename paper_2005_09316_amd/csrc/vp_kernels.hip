@@ -39,6 +39,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "vp_internal.h"
 
 namespace vp {
@@ -147,9 +149,13 @@ __device__ __forceinline__ void derive_one(const DeriveArgs &a, int j) {
   }
 }
 
+// Out of line, so that the table kernels below and the serving kernel's
+// table items run the same machine code and build bitwise identical tables.
+__device__ __noinline__ void derive_ool(const DeriveArgs &a, int j) { derive_one(a, j); }
+
 __global__ void k_derive(DeriveArgs a) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < a.P + a.G + a.S) derive_one(a, j);
+  if (j < a.P + a.G + a.S) derive_ool(a, j);
 }
 
 // S_j(nu_k) = S_ref (nu_k / nu_ref)^alpha * B_j(nu_k) for flat index
@@ -179,9 +185,11 @@ __device__ __forceinline__ void flux_one(const FluxArgs &a, int64_t idx) {
   a.d.flux64[idx] = S;
 }
 
+__device__ __noinline__ void flux_ool(const FluxArgs &a, int64_t idx) { flux_one(a, idx); }
+
 __global__ void k_flux(FluxArgs a) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < (int64_t)a.J * a.Kpad) flux_one(a, idx);
+  if (idx < (int64_t)a.J * a.Kpad) flux_ool(a, idx);
 }
 
 // Coefficient tiles.  Signed coefficients C''[n1][n2] = C[n1][n2] (-1)^floor((n1+n2)/2),
@@ -1228,10 +1236,10 @@ __device__ __noinline__ void serve_table_item(const ServeJobDesc &job, int64_t i
   const int64_t nder = (J + kTileRows - 1) / kTileRows;
   if (item < nder) {
     const int64_t j = item * kTileRows + tid;
-    if (j < J) derive_one(job.da, (int)j);
+    if (j < J) derive_ool(job.da, (int)j);
   } else {
     const int64_t idx = (item - nder) * kTileRows + tid;
-    if (idx < (int64_t)J * job.fa.Kpad) flux_one(job.fa, idx);
+    if (idx < (int64_t)J * job.fa.Kpad) flux_ool(job.fa, idx);
   }
 }
 
@@ -1345,8 +1353,11 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       __syncthreads();
       continue;
     }
-    if (tid == 0 && tile == 0)
-      __hip_atomic_store(&H->started[slot], job.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (tid == 0 && tile == 0) {
+      // the job's first tile (tiles are claimed in order): its start time, then the flag
+      __hip_atomic_store(&H->started_clk[slot], wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&H->started[slot], job.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     const int rb = (int)(tile % job.a.n_rb), cb = (int)(tile / job.a.n_rb);
     if (job.a.uniform)
       pg_tile<kMixed, true>(job.a, rb, cb, sm.pg);
@@ -1364,8 +1375,10 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       // the host flag follows the last count
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system-scope release: write back, no invalidate
       const uint64_t old = __hip_atomic_fetch_add(&D->done[slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old + 1 == job.done_target)
-        __hip_atomic_store(&H->finished[slot], job.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (old + 1 == job.done_target) {
+        __hip_atomic_store(&H->finished_clk[slot], wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&H->finished[slot], job.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
     __syncthreads();  // LDS (job, tiles) is reused by the next claim
   }
@@ -1375,12 +1388,12 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
 // launchers
 // ---------------------------------------------------------------------------
 
-static hipError_t upload_tables() {
-  static bool done[64] = {false};
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
+// Per-device set-up, once per device and process: the recurrence constants
+// into __constant__ memory.
+static std::once_flag g_init_once[kMaxDevices];
+static hipError_t g_init_err[kMaxDevices];
+
+static hipError_t init_constants() {
   double sq[128], isq[128], half[128], sc[4];
   for (int n = 0; n < 128; ++n) {
     sq[n] = sqrt((double)n);
@@ -1389,12 +1402,27 @@ static hipError_t upload_tables() {
   }
   sc[0] = herm_scale(0, 16);
   for (int k = 1; k < 4; ++k) sc[k] = herm_scale(32 * k - 16, 32 * k + 16);
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_sqn), sq, sizeof(sq));
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_sqn), sq, sizeof(sq));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_isqn1), isq, sizeof(isq));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_half), half, sizeof(half));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_sc), sc, sizeof(sc));
-  if (e == hipSuccess && dev >= 0 && dev < 64) done[dev] = true;
   return e;
+}
+
+hipError_t device_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(g_init_once[dev], [dev]() {
+    // the caller has made `dev` current
+    g_init_err[dev] = init_constants();
+  });
+  return g_init_err[dev];
+}
+
+static hipError_t upload_tables() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  return device_init(dev);
 }
 
 hipError_t launch_derive(const DeriveArgs &a, hipStream_t s) {

@@ -48,6 +48,8 @@ struct DerivedEntry {
   hipEvent_t ready = nullptr;  // recorded after kernels built the tables (null when the serving kernel did)
   hipStream_t ready_stream = nullptr;
   bool building = false;       // true while the serving kernel builds the tables (guarded by ctx->mu)
+  bool serve_built = false;    // built for serving and not handed to a direct call since (guarded by ctx->mu)
+  int serve_users = 0;         // admitted serving jobs that use the tables (guarded by ctx->mu)
 };
 
 struct ProfRecord {
@@ -92,6 +94,15 @@ int serve_derived(vp_ctx *ctx, const struct ::vp_sky *sky, const struct ::vp_obs
                   bool *build);
 bool derived_ready(vp_ctx *ctx, DerivedEntry *d);
 void derived_built(vp_ctx *ctx, DerivedEntry *d);
+// A serving job is done with the pair's tables.
+void serve_release_derived(vp_ctx *ctx, DerivedEntry *d);
+// The tables a serving job was to build were never built (its work was
+// abandoned): drop them, so that no later call finds them ready.
+void serve_abandon_derived(vp_ctx *ctx, DerivedEntry *d);
+// Bytes of tables that serving jobs built and no admitted job or direct call
+// uses, and their release (hipFree: waits for the device).
+uint64_t serve_evictable_bytes(vp_ctx *ctx);
+void serve_evict(vp_ctx *ctx);
 DeriveArgs make_derive_args(const struct ::vp_sky *sky, const struct ::vp_obs *obs, const Derived &d);
 FluxArgs make_flux_args(const struct ::vp_sky *sky, const struct ::vp_obs *obs, const Derived &d);
 void drop_derived(vp_ctx *ctx, uint64_t sky_id, uint64_t obs_id);

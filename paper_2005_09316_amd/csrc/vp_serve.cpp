@@ -44,6 +44,7 @@ struct JobRec {
   int state = kQueued;
   int status = VP_OK;
   uint64_t t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+  uint64_t dev_start = 0, dev_done = 0;  // device wall clock at its first tile's start, last tile's end
   uint64_t footprint = 0;
   int slot = -1;
   uint64_t seq = 0, seq_table = 0;
@@ -221,6 +222,46 @@ static int ensure_kernel(Scheduler *s) {
   return VP_OK;
 }
 
+// The persistent kernel could not be launched, or its launch failed on the
+// device: every running job ends with that error (their tiles share the
+// kernel).  No kernel runs now.  The items still in the ring are retired
+// (head = tail) so that a later launch does not run them into buffers their
+// callers may have freed; tables that were to be built are dropped rather than
+// marked ready; each slot's completion targets are re-read from the device
+// counters, which count only the items that ran, before the slot is reused
+// (a slot whose counters cannot be read stays out of use).
+static void abandon_running(Scheduler *s, int rc) {
+  bool synced = false;
+  std::vector<uint64_t> done(kServeSlots), tdone(kServeSlots);
+  {
+    const uint64_t tail = s->tail;
+    hipError_t e = hipMemcpyAsync(&s->D->head, &tail, sizeof(tail), hipMemcpyHostToDevice, s->aux);
+    if (e == hipSuccess) e = hipMemcpyAsync(done.data(), s->D->done, sizeof(uint64_t) * kServeSlots,
+                                            hipMemcpyDeviceToHost, s->aux);
+    if (e == hipSuccess) e = hipMemcpyAsync(tdone.data(), s->D->tdone, sizeof(uint64_t) * kServeSlots,
+                                            hipMemcpyDeviceToHost, s->aux);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->aux);
+    synced = e == hipSuccess;
+  }
+  // jobs waiting for tables that an abandoned owner was to build let go of
+  // them before the owner drops them
+  for (JobRec *j : s->running)
+    if (!j->owner) serve_release_derived(s->ctx, j->d);
+  for (JobRec *j : s->running)
+    if (j->owner) serve_abandon_derived(s->ctx, j->d);
+  for (JobRec *j : s->running) {
+    s->in_use -= j->footprint;
+    s->ring_inflight -= (uint64_t)(j->ntiles + j->ntable);
+    if (synced) {
+      s->slot_target[j->slot] = done[j->slot];
+      s->slot_ttarget[j->slot] = tdone[j->slot];
+      s->free_slots.push_back(j->slot);
+    }
+    finish(s, j, rc);
+  }
+  s->running.clear();
+}
+
 static void scheduler_loop(Scheduler *s) {
   (void)hipSetDevice(s->ctx->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -238,12 +279,18 @@ static void scheduler_loop(Scheduler *s) {
         continue;
       }
       const uint64_t st = __atomic_load_n(&s->H->started[j->slot], __ATOMIC_ACQUIRE);
-      if (j->t_start == 0 && st == j->seq) j->t_start = now_ns();
+      if (j->t_start == 0 && st == j->seq) {
+        j->t_start = now_ns();
+        j->dev_start = __atomic_load_n(&s->H->started_clk[j->slot], __ATOMIC_RELAXED);
+      }
       const uint64_t fin = __atomic_load_n(&s->H->finished[j->slot], __ATOMIC_ACQUIRE);
       if (fin == j->seq) {
+        if (j->dev_start == 0) j->dev_start = __atomic_load_n(&s->H->started_clk[j->slot], __ATOMIC_RELAXED);
+        j->dev_done = __atomic_load_n(&s->H->finished_clk[j->slot], __ATOMIC_RELAXED);
         s->in_use -= j->footprint;
         s->ring_inflight -= (uint64_t)(j->ntiles + j->ntable);
         s->free_slots.push_back(j->slot);
+        serve_release_derived(s->ctx, j->d);
         finish(s, j, VP_OK);
         s->running[i] = s->running.back();
         s->running.pop_back();
@@ -256,9 +303,15 @@ static void scheduler_loop(Scheduler *s) {
       JobRec *j = s->queue.front();
       const uint64_t J = (uint64_t)j->job.sky->P + j->job.sky->G + j->job.sky->S;
       const uint64_t table_items = (J + kTileRows - 1) / kTileRows + (J * j->job.obs->Kpad + kTileRows - 1) / kTileRows;
-      if (s->free_slots.empty() || s->ring_inflight + (uint64_t)j->ntiles + table_items > kRingSize ||
-          s->in_use + j->footprint > s->ctx->budget)
-        break;
+      if (s->free_slots.empty() || s->ring_inflight + (uint64_t)j->ntiles + table_items > kRingSize) break;
+      // the budget covers admitted jobs and the tables that finished serving
+      // jobs built and nothing else uses; those are released when they stand
+      // in the way of the next job
+      if (s->in_use + j->footprint > s->ctx->budget) break;
+      if (s->in_use + serve_evictable_bytes(s->ctx) + j->footprint > s->ctx->budget) {
+        serve_evict(s->ctx);
+        if (s->in_use + serve_evictable_bytes(s->ctx) + j->footprint > s->ctx->budget) break;
+      }
       s->queue.pop_front();
       int rc = admit(s, j);
       if (rc != VP_OK)
@@ -268,16 +321,7 @@ static void scheduler_loop(Scheduler *s) {
     }
     if (!s->running.empty()) {
       int rc = ensure_kernel(s);
-      if (rc != VP_OK) {
-        // a device error ends every running job with that error
-        for (JobRec *j : s->running) {
-          s->in_use -= j->footprint;
-          s->ring_inflight -= (uint64_t)(j->ntiles + j->ntable);
-          if (j->owner) derived_built(s->ctx, j->d);
-          finish(s, j, rc);
-        }
-        s->running.clear();
-      }
+      if (rc != VP_OK) abandon_running(s, rc);
     }
     if (s->quit && s->queue.empty() && s->running.empty()) break;
     if (s->queue.empty() && s->running.empty())
@@ -318,8 +362,9 @@ static int start_scheduler(vp_ctx *ctx, Scheduler **out) {
     delete s;
     return rc;
   }
-  // a workgroup gives up after 20 ms without work; the scheduler relaunches
-  s->idle_ticks = (uint64_t)(rate_khz > 0 ? rate_khz : 100000) * 20;
+  // the workgroups exit together after 2 ms without work (the device is then
+  // free for other kernels); the scheduler relaunches when items wait
+  s->idle_ticks = (uint64_t)(rate_khz > 0 ? rate_khz : 100000) * 2;
   s->slot_target.assign(kServeSlots, 0);
   s->slot_ttarget.assign(kServeSlots, 0);
   for (int i = kServeSlots - 1; i >= 0; --i) s->free_slots.push_back(i);
@@ -431,6 +476,8 @@ int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res) {
   res->t_admit = j->t_admit;
   res->t_start = j->t_start;
   res->t_done = j->t_done;
+  res->dev_first_tile = j->dev_start;
+  res->dev_last_tile = j->dev_done;
   s->jobs.erase(it);
   delete j;
   return VP_OK;

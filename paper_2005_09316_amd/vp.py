@@ -75,7 +75,8 @@ class vp_job(ctypes.Structure):
 
 class vp_job_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_uint64), ("t_admit", ctypes.c_uint64),
-                ("t_start", ctypes.c_uint64), ("t_done", ctypes.c_uint64)]
+                ("t_start", ctypes.c_uint64), ("t_done", ctypes.c_uint64),
+                ("dev_first_tile", ctypes.c_uint64), ("dev_last_tile", ctypes.c_uint64)]
 
 
 _lib = None
@@ -230,14 +231,15 @@ def vp_submit(ctx: int, kind: int, sky: int, obs: int, precision: int, dtype: in
 
 
 def vp_poll(ctx: int, ticket: int) -> Optional[dict]:
-    """dict(status, t_submit, t_admit, t_start, t_done) when done, None if pending."""
+    """dict(status, t_submit, t_admit, t_start, t_done, dev_first_tile, dev_last_tile) when done, None if
+    pending."""
     r = vp_job_result()
     rc = load().vp_poll(ctx, int(ticket), ctypes.byref(r))
     if rc == VP_EAGAIN:
         return None
     _check(rc)
     return {"status": r.status, "t_submit": r.t_submit, "t_admit": r.t_admit, "t_start": r.t_start,
-            "t_done": r.t_done}
+            "t_done": r.t_done, "dev_first_tile": r.dev_first_tile, "dev_last_tile": r.dev_last_tile}
 
 
 def vp_job_footprint(ctx: int, kind: int, sky: int, obs: int, precision: int, dtype: int, vis_dev: int = 0) -> int:

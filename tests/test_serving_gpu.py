@@ -99,9 +99,110 @@ def test_mix_equals_alone_and_oracle(ctx):
         r = res[tickets[i]]
         assert r["t_submit"] <= r["t_admit"] <= r["t_start"] <= r["t_done"]
     _log("10 uneven jobs: mix == alone bitwise, all within 1e-6 of the oracle")
+    pairs = _overlapping_pairs([res[t] for t in tickets])
+    _log("  %d pairs of jobs had tiles on the device at the same time" % pairs)
+    assert pairs > 0
     for oh, sh in handles:
         vp.vp_destroy_sky(sh)
         vp.vp_destroy_obs(oh)
+
+
+def _overlapping_pairs(results):
+    """Pairs of jobs whose device intervals [first tile start, last tile end]
+    intersect (device wall clock, one clock per device)."""
+    iv = [(r["dev_first_tile"], r["dev_last_tile"]) for r in results if r["dev_last_tile"]]
+    n = 0
+    for i in range(len(iv)):
+        for j in range(i + 1, len(iv)):
+            if iv[i][0] < iv[j][1] and iv[j][0] < iv[i][1]:
+                n += 1
+    return n
+
+
+def _bits_equal(a, b):
+    import torch
+    return bool(torch.equal(torch.view_as_real(a).contiguous().view(torch.int32),
+                            torch.view_as_real(b).contiguous().view(torch.int32)))
+
+
+def _stream_jobs():
+    """Requests of the serving stream (seeded), from its largest (256 tiles,
+    330-384 channels, up to 14 times, shapelets of order up to 77) to small
+    ones, plus a 256-tile x 384-channel subtract job with two N = 80
+    shapelets drawn by the stream's recipe."""
+    import math
+    reqs = synth.make_requests()
+    pick = [130, 184, 172, 252, 0, 1, 2, 3]
+    jobs = [(reqs[i].kind, reqs[i].obs, reqs[i].sky, reqs[i].noise_seed, "request %d" % i) for i in pick]
+    rng = np.random.default_rng(31337)
+    obs = synth.make_obs(rng, 256, 2, synth.channels(182e6, 80e3, 384))
+    sky = synth.make_sky(rng, n_point=int(rng.poisson(2000)), n_gauss=int(rng.poisson(200)), shapelet_nmax=[80, 80],
+                         cap_rad=math.radians(10.0), point_flux=synth._pl(0.05, 50.0),
+                         shapelet_sref=synth._lu(1.0, 100.0), tau=20.0)
+    jobs.append(("subtract", obs, sky, 4242, "256 tiles x 384 channels, N = 80"))
+    return jobs
+
+
+def test_stream_requests_mix_alone_oracle():
+    """Serving-stream-sized jobs submitted together to fresh sky and
+    observation handles, so that the persistent kernel builds every pair's
+    tables itself; each result must equal vp_predict / vp_subtract on separate
+    handles bit for bit and the oracle on sampled rows within 1e-6 of the
+    total flux; some jobs' tiles must run on the device at the same time."""
+    import torch
+    jobs = _stream_jobs()
+    ctx = vp.vp_create_ctx(0, 0)
+    s = torch.cuda.current_stream()
+    try:
+        alone, mixed, handles = [], [], []
+        for kind, obs, sky, seed, name in jobs:
+            shape = (obs.n_time, obs.n_bl, obs.n_chan)
+            g = torch.Generator(device="cuda").manual_seed(seed)
+            data = torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+            a = data.clone() if kind == "subtract" else torch.full_like(data, float("nan"))
+            m = data.clone() if kind == "subtract" else torch.full_like(data, float("nan"))
+            oa, sa = vp.vp_create_obs(ctx, obs), vp.vp_create_sky(ctx, sky)
+            fn = vp.vp_subtract if kind == "subtract" else vp.vp_predict
+            fn(ctx, sa, oa, vp.VP_PREC_MIXED, vp.VP_C64, a.data_ptr(), s.cuda_stream)
+            s.synchronize()
+            vp.vp_destroy_sky(sa)
+            vp.vp_destroy_obs(oa)
+            alone.append(a)
+            mixed.append(m)
+            handles.append((vp.vp_create_obs(ctx, obs), vp.vp_create_sky(ctx, sky)))
+            _log("%s: %s, %d vis, %d points, %d Gaussians, shapelets %s"
+                 % (name, kind, obs.n_vis, sky.n_point, sky.n_gauss, list(np.asarray(sky.s_nmax))))
+            del data
+        torch.cuda.synchronize()
+        tickets = []
+        for (kind, obs, sky, seed, name), (oh, sh), m in zip(jobs, handles, mixed):
+            k = vp.VP_JOB_SUBTRACT if kind == "subtract" else vp.VP_JOB_PREDICT
+            tickets.append(vp.vp_submit(ctx, k, sh, oh, vp.VP_PREC_MIXED, vp.VP_C64, m.data_ptr()))
+        res = _wait(ctx, tickets, timeout=100.0)
+        assert all(res[t]["status"] == vp.VP_OK for t in tickets)
+        for i, ((kind, obs, sky, seed, name), a, m) in enumerate(zip(jobs, alone, mixed)):
+            assert _bits_equal(m, a), "%s differs between serving (tables built in the kernel) and alone" % name
+            nrows = obs.n_time * obs.n_bl
+            rows = np.sort(np.random.default_rng(700 + i).choice(nrows, min(8, nrows), replace=False))
+            got = m.reshape(nrows, obs.n_chan)[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+            ref = oracle.predict(obs, sky, rows=rows)
+            if kind == "subtract":
+                g = torch.Generator(device="cuda").manual_seed(seed)
+                d0 = torch.randn((obs.n_time, obs.n_bl, obs.n_chan), dtype=torch.complex64, device="cuda",
+                                 generator=g).reshape(nrows, obs.n_chan)
+                ref = d0[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.complex128) - ref
+                del d0
+            err = oracle.error_metric(got.astype(np.complex128), ref, obs, sky)
+            _log("  %s: serving == alone bitwise; sampled error / total flux = %.3e" % (name, err))
+            assert err <= 1e-6, (name, err)
+        pairs = _overlapping_pairs([res[t] for t in tickets])
+        _log("  %d pairs of jobs had tiles on the device at the same time" % pairs)
+        assert pairs > 0
+        for oh, sh in handles:
+            vp.vp_destroy_sky(sh)
+            vp.vp_destroy_obs(oh)
+    finally:
+        vp.vp_destroy_ctx(ctx)
 
 
 def test_budget_admission_fifo():
