@@ -100,8 +100,11 @@ def _shp_mfma_flops(nmax, n_vis, mode):
     return total * n_vis / 32.0
 
 
-def shapelet_contraction(reps=5, check_rows=48):
-    """Shapelet kernel on the Fornax-like workload, per contraction mode."""
+def shapelet_contraction(reps=5):
+    """Shapelet kernel on the Fornax-like workload, per precision path: time per
+    launch (HIP events on the launch stream), contraction FLOP/s and, against the
+    oracle over every visibility of the workload, the maximum error relative to
+    the total flux (complex128 output, so that the figure is the path's own)."""
     import torch
 
     import oracle
@@ -116,12 +119,16 @@ def shapelet_contraction(reps=5, check_rows=48):
     stream = torch.cuda.current_stream()
     ptot = sum((int(n) + 1) * (int(n) + 2) // 2 for n in sky.s_nmax)
     alg_flops = 2.0 * ptot * obs.n_vis
-    rows = np.sort(np.random.default_rng(6).choice(nrows, check_rows, replace=False))
-    ref = oracle.predict(obs, sky, rows=rows)
+    t0 = time.time()
+    ref = oracle.predict(obs, sky).reshape(nrows, K)
+    _log("fornax-like oracle over all %d visibilities: %.1f s on %d threads"
+         % (obs.n_vis, time.time() - t0, oracle.max_threads()))
     res = {"workload": synth.CONFIG_NAMES[2], "n_vis": obs.n_vis, "nmax": [int(n) for n in sky.s_nmax],
-           "algorithmic_flops_per_launch": alg_flops, "modes": {}}
+           "algorithmic_flops_per_launch": alg_flops, "error": "max over all visibilities vs the oracle, "
+           "relative to the channel's total flux", "modes": {}}
     for name, prec, mode, peak in (("mixed_bf16x3", vp.VP_PREC_MIXED, "bf16x3", MFMA_PEAK_BF16),
-                                   ("mixed_f32mma", vp.VP_PREC_MIXED_F32MMA, "f32", MFMA_PEAK_F32),
+                                   ("mixed_bf16x2", vp.VP_PREC_MIXED_BF16X2, "bf16x2", MFMA_PEAK_BF16),
+                                   ("fp32_only", vp.VP_PREC_FP32, "f32", MFMA_PEAK_F32),
                                    ("fp64_valu", vp.VP_PREC_FP64, None, VALU_PEAK_F64),
                                    ("lut_valu", vp.VP_PREC_LUT, None, VALU_PEAK_F64)):
         vp.vp_predict(ctx, sh, oh, prec, vp.VP_C128, out.data_ptr(), stream.cuda_stream)
@@ -134,13 +141,13 @@ def shapelet_contraction(reps=5, check_rows=48):
         c, t = vp.vp_profile_read(ctx)
         vp.vp_profile(ctx, False)
         ms = float(t[2] / max(c[2], 1))
-        got = out[torch.as_tensor(rows, device="cuda")].cpu().numpy()
-        err = oracle.error_metric(got, ref, obs, sky)
+        err = oracle.error_metric(out.cpu().numpy(), ref, obs, sky)
         r = {"kernel_ms": round(ms, 4),
              "algorithmic_tflops": round(alg_flops / ms / 1e9, 2),
              "frac_of_fp32_mfma_peak": round(alg_flops / ms / 1e9 / MFMA_PEAK_F32, 4),
              "own_peak_tflops": peak,
-             "sampled_err_vs_oracle": err}
+             "max_err_vs_oracle": err,
+             "gate": {"mixed_bf16x3": 1e-6, "fp64_valu": 1e-11}.get(name)}
         if mode is not None:
             issued = _shp_mfma_flops(sky.s_nmax, obs.n_vis, mode)
             r["issued_mfma_tflops"] = round(issued / ms / 1e9, 2)
@@ -150,7 +157,7 @@ def shapelet_contraction(reps=5, check_rows=48):
             r["frac_of_own_peak"] = round(alg_flops / ms / 1e9 / peak, 4)
         res["modes"][name] = r
         _log("shapelet kernel %s: %.3f ms, %.1f TFLOP/s algorithmic (%.1f%% of FP32 MFMA peak), "
-             "err %.2e" % (name, ms, r["algorithmic_tflops"], 100 * r["frac_of_fp32_mfma_peak"], err))
+             "max err %.2e" % (name, ms, r["algorithmic_tflops"], 100 * r["frac_of_fp32_mfma_peak"], err))
     vp.vp_destroy_sky(sh)
     vp.vp_destroy_obs(oh)
     vp.vp_destroy_ctx(ctx)

@@ -67,13 +67,16 @@ extern "C" {
 #define VP_PREC_MIXED 1       /* FP64 phase + range reduction; FP32 sincos/envelopes, FP32 partial
                                  sums of 8 terms added into FP64;
                                  FP64 Hermite recurrence; shapelet contraction on MFMA with the
-                                 coefficients and Hermite values split into 3 BF16 parts (6 products,
-                                 FP32 accumulation, folded into FP64 per 32 orders) */
+                                 coefficients and Hermite values split into 3 BF16 parts from their
+                                 FP64 values (6 products, FP32 accumulation, folded into FP64 per
+                                 32 orders) */
 #define VP_PREC_MIXED_BF16 2  /* the same path as VP_PREC_MIXED (explicit name of its contraction) */
 #define VP_PREC_FP32 3        /* FP32 everywhere, phase included (reported, not accurate) */
 #define VP_PREC_MIXED_BF16X2 4 /* as MIXED, contraction as 2-way BF16 split (3 products; reported) */
-#define VP_PREC_MIXED_F32MMA 5 /* as MIXED, contraction on FP32 MFMA folded into FP64 every 8 orders
-                                  (reported: ~1e-6 of total flux on heavily cancelling coefficients) */
+#define VP_PREC_MIXED_F32MMA 5 /* retired (refused with VP_EINVAL): a contraction on FP32 MFMA was
+                                  both slower than the 3-way BF16 split and, at ~1e-6 of the total
+                                  flux on heavily cancelling coefficients, not inside the mixed
+                                  path's bar; the value stays reserved */
 #define VP_PREC_LUT 6         /* as FP64, but the shapelet basis read from a 1-D FP32 table of the
                                  Hermite functions (8192 samples over 0 <= x < 32, linear
                                  interpolation), as the paper's simulator does (Sec. 3.2);

@@ -388,6 +388,8 @@ int check_call(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision,
   if (sky->ctx != ctx || obs->ctx != ctx) return set_error(VP_EINVAL, "sky or observation belongs to another context");
   if (precision < VP_PREC_FP64 || precision > VP_PREC_LUT)
     return set_error(VP_EINVAL, "unknown precision %d", precision);
+  if (precision == VP_PREC_MIXED_F32MMA)
+    return set_error(VP_EINVAL, "precision %d (FP32 MFMA contraction) is retired", precision);
   if (dtype != VP_C128 && dtype != VP_C64) return set_error(VP_EINVAL, "unknown dtype %d", dtype);
   if (!vis) return set_error(VP_EINVAL, "NULL visibility buffer");
   return VP_OK;

@@ -20,16 +20,17 @@
 //               path: Kahan-compensated FP32 sums).
 //   k_shp_mfma  shapelets.  Per (visibility, shapelet): rotate uvw into the
 //               shapelet's frame, walk the rescaled Hermite recurrence for
-//               both axes (FP64: it costs the same issue slots as FP32 on this
-//               chip and removes the argument-rounding and underflow error of
-//               an FP32 recurrence), contract against the signed coefficient
-//               matrix on MFMA (n1 on M, n2 on K split by parity into
-//               real/imaginary accumulators, 32 visibilities on N; 32 x 32
-//               blocks that meet the n1 + n2 <= N triangle only;
-//               v_mfma_f32_32x32x16_bf16 on 3-way BF16 splits, or
-//               v_mfma_f32_32x32x2_f32), fold the n1 sum against the first
-//               axis in FP64 in the MFMA output layout, and add flux x
-//               envelope x phase into an FP64 accumulator held in LDS.
+//               both axes (FP64 on the mixed path: it costs the same issue
+//               slots as FP32 on this chip and removes the argument-rounding
+//               and underflow error of an FP32 recurrence), contract against
+//               the signed coefficient matrix on MFMA (n1 on M, n2 on K split
+//               by parity into real/imaginary accumulators, 32 visibilities on
+//               N; 32 x 32 blocks that meet the n1 + n2 <= N triangle only;
+//               v_mfma_f32_32x32x16_bf16 on 3-way BF16 splits of the FP64
+//               values on the mixed path, v_mfma_f32_32x32x2_f32 on the
+//               FP32-only path), fold each block's n1 sum against the first
+//               axis (FP64 on the mixed path), and add flux x envelope x
+//               phase into an FP64 accumulator held in LDS.
 //   k_shp_fp64  the FP64 path of the shapelet term on the vector ALU (and
 //               the lookup-table variant of the basis).
 //
@@ -272,12 +273,14 @@ __global__ void k_tiles(TileBuildArgs a) {
     pair_coords(q, p, ch, mb);
     const int n1 = 32 * mb + (lane & 31), n2 = 32 * ch + 16 * (lane >> 5) + 2 * e + par;
     const double v = signed_coeff(C, N, n1, n2);
-    const float x = v == 0.0 ? 0.f : (float)(v * herm_scale(32 * mb + 16, n1) * herm_scale(32 * ch + 16, n2));
-    const uint16_t hi = bf16_rne(x);
-    const float r1 = x - bf16_to_f(hi);
-    const uint16_t mid = bf16_rne(r1);
-    const float r2 = r1 - bf16_to_f(mid);
-    const uint16_t lo = bf16_rne(r2);
+    // split the FP64 value itself: each residual is formed in FP64 (exactly),
+    // so the three parts carry ~27 bits instead of an FP32 rounding's 24
+    const double x = v == 0.0 ? 0.0 : v * herm_scale(32 * mb + 16, n1) * herm_scale(32 * ch + 16, n2);
+    const uint16_t hi = bf16_rne((float)x);
+    const double r1 = x - (double)bf16_to_f(hi);
+    const uint16_t mid = bf16_rne((float)r1);
+    const double r2 = r1 - (double)bf16_to_f(mid);
+    const uint16_t lo = bf16_rne((float)r2);
     uint16_t *dst = a.abf + a.abf_off[s];
     dst[i] = hi;
     dst[nbf + i] = mid;
@@ -602,6 +605,7 @@ enum Contraction : int { kCmF32 = 0, kCmBf16x2 = 2, kCmBf16x3 = 3 };
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // LDS of the shapelet tile: the coefficient blocks of one shapelet and the
 // tile's visibility sums (one slot per thread and channel, FP64 on the mixed
@@ -649,32 +653,11 @@ __device__ __forceinline__ void half_swap(float &p, float &q) {
   p = __uint_as_float(r[0]);
   q = __uint_as_float(r[1]);
 }
-__device__ __forceinline__ void half_swap(double &p, double &q) {
-  const uint64_t pu = (uint64_t)__double_as_longlong(p), qu = (uint64_t)__double_as_longlong(q);
-  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)pu, (uint32_t)qu, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(pu >> 32), (uint32_t)(qu >> 32), false, false);
-  p = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
-  q = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+__device__ __forceinline__ void half_swap(uint32_t &p, uint32_t &q) {
+  const auto r = __builtin_amdgcn_permlane32_swap(p, q, false, false);
+  p = r[0];
+  q = r[1];
 }
-
-template <int CM>
-__device__ __forceinline__ floatx16 bf16_products(bf16x8 ah, bf16x8 am, bf16x8 al, bf16x8 bh, bf16x8 bm,
-                                                  bf16x8 bl) {
-  const floatx16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  floatx16 d;
-  // smallest products first
-  if (CM == kCmBf16x3) {
-    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, z, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, d, 0, 0, 0);
-  } else {
-    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, z, 0, 0, 0);
-  }
-  d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, d, 0, 0, 0);
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, d, 0, 0, 0);
-}
-
 // Fold one 32 x 32 block's FP32 accumulators into the DOT-precision sums:
 // walk the first-axis recurrence (rescaled, psi_next) over the block's rows
 // n0 + 8 g + r (this lane's visibility), 8 rows at a time, bring each row value to the lanes
@@ -724,21 +707,19 @@ __device__ __forceinline__ void shp_fold(REC x, REC &prev, REC &cur, int n0, int
   }
 }
 
-// One tile: kTileRows rows x kShpChan channels starting at channel block cb.
-// Lane l of wave w owns row 64 w + l and runs both Hermite recurrences of its
-// visibility (REC: FP64 on the mixed paths).  The MFMA's N dimension is 32
-// visibilities: group 0 is the lower half-wave's, group 1 the upper's, and
-// each operand value reaches the lane that supplies it through one half_swap
-// per pair of values.  M is a 32-row block of the first axis, K runs over the
-// second axis's orders with even orders in one accumulator and odd orders in
-// the other; after each 32 x 32 coefficient block the FP32 accumulators are
-// folded into a DOT-precision dot product with the first axis's values.  The
-// second axis is walked once per (visibility, channel); the first axis's
-// block values are recomputed per chunk from saved start values.
-template <typename REC, typename DOT, int CM = kCmF32>
-__device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpSmem<CM> &sm) {
+// One tile of the FP32-only path's shapelet pass: kTileRows rows x kShpChan
+// channels starting at channel block cb.  Lane l of wave w owns row 64 w + l
+// and runs both Hermite recurrences of its visibility in FP32.  The MFMA's N
+// dimension is 32 visibilities: group 0 is the lower half-wave's, group 1 the
+// upper's, and each operand value reaches the lane that supplies it through
+// one half_swap per pair of values.  M is a 32-row block of the first axis, K
+// runs over the second axis's orders (v_mfma_f32_32x32x2f32, K steps of 4
+// orders inside the triangle) with even orders in one accumulator and odd
+// orders in the other, folded into FP32 sums every 4 steps.
+__device__ __forceinline__ void shp_tile_f32(const TileArgs &a, int rb, int cb, ShpSmem<kCmF32> &sm) {
+  using REC = float;
+  using DOT = float;
   constexpr int KB = kShpChan;
-  constexpr int parts = CM == kCmBf16x3 ? 3 : 2;
   const int k0 = cb * KB;
   const int tid = threadIdx.x, lane = tid & 63;
   const int64_t row = (int64_t)rb * kTileRows + tid;
@@ -773,15 +754,10 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
     const int q = N / 32;
     const int npairs = (q + 1) * (q + 2) / 2;
     __syncthreads();  // the previous shapelet's blocks are no longer read
-    if constexpr (CM == kCmF32) {
+    {
       const uint4 *src = (const uint4 *)(a.t.a32 + a.t.a32_off[j]);
       uint4 *dst = (uint4 *)&sm.A[0];
       for (int i = tid; i < npairs * kA32PerPair / 4; i += kTileRows) dst[i] = src[i];
-    } else {
-      // the first `parts` split parts; each part holds npairs blocks
-      const uint4 *src = (const uint4 *)(a.t.abf + a.t.abf_off[j]);
-      uint4 *dst = &sm.A[0];
-      for (int i = tid; i < parts * npairs * kAbfPerPair / 8; i += kTileRows) dst[i] = src[i];
     }
     const double *fr = a.d.sframe + 12 * j;
     const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
@@ -793,8 +769,7 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
     for (int c = 0; c < KB; ++c) {
       if (k0 + c >= K) break;
       const double f = a.fk[k0 + c];
-      const DOT S = sizeof(DOT) == 8 ? (DOT)a.d.flux64[(int64_t)jg * a.Kpad + k0 + c]
-                                     : (DOT)a.d.flux32[(int64_t)jg * a.Kpad + k0 + c];
+      const DOT S = (DOT)a.d.flux32[(int64_t)jg * a.Kpad + k0 + c];
       const REC xa = (REC)am * (REC)f;
       const REC xb = (REC)bm * (REC)f;
       // rescaled walks (psi_next): block or chunk k of 32 orders uses base
@@ -839,122 +814,51 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
           pb_m1 = prev * rs;
           pb_n = cur * rs;
         }
-        // B operands of both groups.  FP32 MFMA (K = 2): lanes of half h
-        // supply orders 4 s + 2 h + parity of K step s, stored at [2 s + parity].
-        // BF16 MFMA (K = 16): lanes of half h supply orders 16 h + 2 e + parity,
-        // stored at [2 e + parity].
+        // B operands of both groups (K = 2): lanes of half h supply orders
+        // 4 s + 2 h + parity of K step s, stored at [2 s + parity]
         float bg0[16], bg1[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-          const int lo = CM == kCmF32 ? 4 * (t >> 1) + (t & 1) : t;
-          const int hi = CM == kCmF32 ? lo + 2 : t + 16;
-          float p = ob[lo], qv = ob[hi];
+          const int lo = 4 * (t >> 1) + (t & 1);
+          float p = ob[lo], qv = ob[lo + 2];
           half_swap(p, qv);
           bg0[t] = p;
           bg1[t] = qv;
-        }
-        bf16x8 Bh[2][2], Bm[2][2], Bl[2][2];  // [group][parity]
-        if (CM != kCmF32) {
-          // x = hi + mid + lo, each part rounded to nearest; two values per
-          // conversion instruction.  Element e of either half carries order
-          // 16 h + 2 e + parity of the chunk: when fewer than 16 orders of the
-          // chunk are inside the triangle, elements past them are zero in
-          // both halves and are not split.
-          const int rch = N - 32 * ch;
-          const int ne = rch < 16 ? rch / 4 + 1 : 4;  // element pairs (e, e + 1) to split
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            if (e / 2 < ne) {
-#pragma unroll
-              for (int g = 0; g < 2; ++g)
-#pragma unroll
-                for (int par = 0; par < 2; ++par) {
-                  const float2v x = {g ? bg1[2 * e + par] : bg0[2 * e + par],
-                                     g ? bg1[2 * e + 2 + par] : bg0[2 * e + 2 + par]};
-                  const bf16x2v h = __builtin_convertvector(x, bf16x2v);
-                  const float2v r = x - __builtin_convertvector(h, float2v);
-                  const bf16x2v m = __builtin_convertvector(r, bf16x2v);
-                  const bf16x2v l = __builtin_convertvector(r - __builtin_convertvector(m, float2v), bf16x2v);
-                  Bh[g][par][e] = h[0];
-                  Bh[g][par][e + 1] = h[1];
-                  Bm[g][par][e] = m[0];
-                  Bm[g][par][e + 1] = m[1];
-                  Bl[g][par][e] = l[0];
-                  Bl[g][par][e + 1] = l[1];
-                }
-            } else {
-#pragma unroll
-              for (int g = 0; g < 2; ++g)
-#pragma unroll
-                for (int par = 0; par < 2; ++par) {
-                  const __bf16 z = (__bf16)0.f;
-                  Bh[g][par][e] = z;
-                  Bh[g][par][e + 1] = z;
-                  Bm[g][par][e] = z;
-                  Bm[g][par][e + 1] = z;
-                  Bl[g][par][e] = z;
-                  Bl[g][par][e + 1] = z;
-                }
-            }
-          }
         }
         const int nmb = q - ch + 1;
 #pragma unroll
         for (int mb = 0; mb < kMBMax; ++mb) {
           if (mb >= nmb) break;
           const int p = pbase + mb;
-          // first axis, this lane's visibility: rows 32 mb + 8 g + r, walked
-          // 8 rows at a time and folded as they come.  Accumulator register
-          // i of a lane in half h holds block row 8 (i / 4) + 4 h + i % 4, of
-          // parity i % 2.
           REC prev = sam[mb], cur = san[mb];
           // 8-row groups of this block that meet the triangle; all four while
           // chunk 0 walks towards a further block's start values
           const int ng = (ch == 0 && mb < q) ? 4 : min(4, (N - 32 * (ch + mb)) / 8 + 1);
-          if constexpr (CM == kCmF32) {
-            // K steps of this block inside the triangle: 32 (ch + mb) + 4 s <= N,
-            // in two halves of 4 steps, each folded as soon as it is summed
-            // (an FP32 sum over all 8 steps loses ~1.5x more to the
-            // coefficients' cancellation); the second fold walks the rows again
-            const int smax = min(8, (N - 32 * (ch + mb)) / 4 + 1);
-            const float *Ap = &sm.A[p * kA32PerPair];
-            const REC prev0 = prev, cur0 = cur;
-            const int nh = smax > 4 ? 2 : 1;
+          // K steps of this block inside the triangle: 32 (ch + mb) + 4 s <= N,
+          // in two halves of 4 steps, each folded as soon as it is summed; the
+          // second fold walks the rows again
+          const int smax = min(8, (N - 32 * (ch + mb)) / 4 + 1);
+          const float *Ap = &sm.A[p * kA32PerPair];
+          const REC prev0 = prev, cur0 = cur;
+          const int nh = smax > 4 ? 2 : 1;
 #pragma nounroll
-            for (int hf = 0; hf < nh; ++hf) {
-              floatx16 E0 = zero16, O0 = zero16, E1 = zero16, O1 = zero16;
+          for (int hf = 0; hf < nh; ++hf) {
+            floatx16 E0 = zero16, O0 = zero16, E1 = zero16, O1 = zero16;
 #pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                const int st = 4 * hf + k;
-                if (st < smax) {
-                  const float ae = Ap[st * 64 + lane], ao = Ap[(8 + st) * 64 + lane];
-                  const float b0e = hf ? bg0[8 + 2 * k] : bg0[2 * k], b0o = hf ? bg0[9 + 2 * k] : bg0[2 * k + 1];
-                  const float b1e = hf ? bg1[8 + 2 * k] : bg1[2 * k], b1o = hf ? bg1[9 + 2 * k] : bg1[2 * k + 1];
-                  E0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, b0e, E0, 0, 0, 0);
-                  O0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, b0o, O0, 0, 0, 0);
-                  E1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, b1e, E1, 0, 0, 0);
-                  O1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, b1o, O1, 0, 0, 0);
-                }
+            for (int k = 0; k < 4; ++k) {
+              const int st = 4 * hf + k;
+              if (st < smax) {
+                const float ae = Ap[st * 64 + lane], ao = Ap[(8 + st) * 64 + lane];
+                const float b0e = hf ? bg0[8 + 2 * k] : bg0[2 * k], b0o = hf ? bg0[9 + 2 * k] : bg0[2 * k + 1];
+                const float b1e = hf ? bg1[8 + 2 * k] : bg1[2 * k], b1o = hf ? bg1[9 + 2 * k] : bg1[2 * k + 1];
+                E0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, b0e, E0, 0, 0, 0);
+                O0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, b0o, O0, 0, 0, 0);
+                E1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, b1e, E1, 0, 0, 0);
+                O1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, b1o, O1, 0, 0, 0);
               }
-              prev = prev0;
-              cur = cur0;
-              shp_fold<REC, DOT>(xa, prev, cur, 32 * mb, ng, E0, O0, E1, O1, xr0, xi0, xr1, xi1);
             }
-          } else {
-            const __bf16 *Ab = (const __bf16 *)&sm.A[0];
-            const int part = npairs * kAbfPerPair;
-            const int oe = p * kAbfPerPair + lane * 8, oo = oe + 64 * 8;
-            const bf16x8 Aeh = *(const bf16x8 *)(Ab + oe), Aoh = *(const bf16x8 *)(Ab + oo);
-            const bf16x8 Aem = *(const bf16x8 *)(Ab + part + oe), Aom = *(const bf16x8 *)(Ab + part + oo);
-            bf16x8 Ael = Aem, Aol = Aom;
-            if (CM == kCmBf16x3) {
-              Ael = *(const bf16x8 *)(Ab + 2 * part + oe);
-              Aol = *(const bf16x8 *)(Ab + 2 * part + oo);
-            }
-            const floatx16 E0 = bf16_products<CM>(Aeh, Aem, Ael, Bh[0][0], Bm[0][0], Bl[0][0]);
-            const floatx16 O0 = bf16_products<CM>(Aoh, Aom, Aol, Bh[0][1], Bm[0][1], Bl[0][1]);
-            const floatx16 E1 = bf16_products<CM>(Aeh, Aem, Ael, Bh[1][0], Bm[1][0], Bl[1][0]);
-            const floatx16 O1 = bf16_products<CM>(Aoh, Aom, Aol, Bh[1][1], Bm[1][1], Bl[1][1]);
+            prev = prev0;
+            cur = cur0;
             shp_fold<REC, DOT>(xa, prev, cur, 32 * mb, ng, E0, O0, E1, O1, xr0, xi0, xr1, xi1);
           }
           if (mb + 1 < kMBMax && ch == 0 && mb < q) {
@@ -968,19 +872,8 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
       half_swap(xr0, xr1);
       half_swap(xi0, xi1);
       const DOT xr = xr0 + xr1, xi = xi0 + xi1;
-      // phase, flux and accumulation
-      DOT cs, sn;
-      if (sizeof(DOT) == 8) {
-        double c8, s8;
-        turns_sincos_f64(t0 * f, c8, s8);
-        cs = (DOT)c8;
-        sn = (DOT)s8;
-      } else {
-        float c4, s4;
-        turns_sincos_f32((float)t0 * (float)f, c4, s4);
-        cs = (DOT)c4;
-        sn = (DOT)s4;
-      }
+      float cs, sn;
+      turns_sincos_f32((float)t0 * (float)f, cs, sn);
       const DOT tr = sgn * S * (xr * cs - xi * sn);
       const DOT ti = sgn * S * (xr * sn + xi * cs);
       sm.acc_re[c][tid] = (double)((DOT)sm.acc_re[c][tid] + tr);
@@ -1000,11 +893,279 @@ __device__ __forceinline__ void shp_tile(const TileArgs &a, int rb, int cb, ShpS
   }
 }
 
-template <typename REC, typename DOT, int CM>
+// ---------------------------------------------------------------------------
+// shapelet tile, BF16-split contraction (mixed path)
+// ---------------------------------------------------------------------------
+
+// The products of one MFMA group: even-n2 (E) and odd-n2 (O) accumulators of
+// one 32 x 32 block, the two chains interleaved; smallest products first:
+// (mid, mid), (lo, hi), (hi, lo), (mid, hi), (hi, mid), (hi, hi), or for the
+// 2-way split (mid, hi), (hi, mid), (hi, hi).
+template <int CM>
+__device__ __forceinline__ void shp_group_mfma(const bf16x8 (&A)[3][2], const bf16x8 (&Bg)[3][2], floatx16 &E,
+                                               floatx16 &O) {
+  const floatx16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (CM == kCmBf16x3) {
+    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][0], Bg[1][0], z, 0, 0, 0);
+    O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][1], Bg[1][1], z, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[2][0], Bg[0][0], E, 0, 0, 0);
+    O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[2][1], Bg[0][1], O, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][0], Bg[2][0], E, 0, 0, 0);
+    O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][1], Bg[2][1], O, 0, 0, 0);
+    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][0], Bg[0][0], E, 0, 0, 0);
+    O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][1], Bg[0][1], O, 0, 0, 0);
+  } else {
+    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][0], Bg[0][0], z, 0, 0, 0);
+    O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][1], Bg[0][1], z, 0, 0, 0);
+  }
+  E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][0], Bg[1][0], E, 0, 0, 0);
+  O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][1], Bg[1][1], O, 0, 0, 0);
+  E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][0], Bg[0][0], E, 0, 0, 0);
+  O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][1], Bg[0][1], O, 0, 0, 0);
+}
+
+// One tile of the mixed path's shapelet pass: kTileRows rows x kShpChan
+// channels starting at channel block cb.  Lane l of wave w owns row 64 w + l
+// and runs both Hermite recurrences of its visibility in FP64 (rescaled,
+// psi_next).  The MFMA's N dimension is 32 visibilities: group 0 is the lower
+// half-wave's, group 1 the upper's.  M is a 32-row block of the first axis, K
+// the second axis's orders, even orders in one accumulator (E) and odd orders
+// in the other (O).
+//   * Second axis, per chunk of 32 orders: each lane walks its own
+//     visibility, splits every value into BF16 parts from its FP64 value
+//     (the residual after the high part is formed in FP64, exactly, so the
+//     parts carry ~27 bits instead of an FP32 rounding's 24; that rounding
+//     measured as the largest single error term of the contraction), packs
+//     them two per register and exchanges half of them with the other half
+//     of the wave, one v_permlane32_swap per register.
+//   * First axis, per block: both groups' MFMAs; then each accumulator
+//     register of group 0 is exchanged with the same register of group 1, so
+//     that every lane holds all 8 rows of each 8-row group for its own
+//     visibility (accumulator register i then holds row 8 (i / 4) + i % 4 in
+//     group 0's set and row 8 (i / 4) + 4 + i % 4 in group 1's); the lane
+//     walks its own first-axis recurrence over the block and folds the rows
+//     into FP64 sums.  No row value crosses lanes.
+// The first axis is walked from order 0 in each chunk, carried from one
+// block into the next (only a chunk's last block is partial).  Sums start
+// from what the point/Gaussian pass left (from zero without one).
+template <int CM>
+__device__ __forceinline__ void shp_tile_bf(const TileArgs &a, int rb, int cb, ShpSmem<CM> &sm) {
+  static_assert(CM == kCmBf16x3 || CM == kCmBf16x2, "BF16-split contraction modes only");
+  constexpr int KB = kShpChan;
+  constexpr int parts = CM == kCmBf16x3 ? 3 : 2;
+  const int k0 = cb * KB;
+  const int tid = threadIdx.x;
+  const int64_t row = (int64_t)rb * kTileRows + tid;
+  const bool valid = row < a.nrows;
+  const int64_t rowc = valid ? row : a.nrows - 1;
+  const int K = a.K;
+
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    double sr = 0, si = 0;
+    if (valid && k0 + c < K && !a.fresh) {
+      const int64_t idx = row * K + k0 + c;
+      if (a.c64) {
+        const float2 x = ((const float2 *)a.vis)[idx];
+        sr = x.x;
+        si = a.conj ? -x.y : x.y;
+      } else {
+        const double2 x = ((const double2 *)a.vis)[idx];
+        sr = x.x;
+        si = a.conj ? -x.y : x.y;
+      }
+    }
+    sm.acc_re[c][tid] = sr;
+    sm.acc_im[c][tid] = si;
+  }
+
+  const double sgn = a.subtract ? -1 : 1;
+  for (int j = 0; j < a.S; ++j) {
+    const int N = a.t.nmax[j];
+    const int q = N / 32;
+    const int npairs = (q + 1) * (q + 2) / 2;
+    __syncthreads();  // the previous shapelet's blocks are no longer read
+    {
+      const uint4 *src = (const uint4 *)(a.t.abf + a.t.abf_off[j]);
+      uint4 *dst = &sm.A[0];
+      for (int i = tid; i < parts * npairs * kAbfPerPair / 8; i += kTileRows) dst[i] = src[i];
+    }
+    const double *fr = a.d.sframe + 12 * j;
+    const double u = a.uvw[3 * rowc], v = a.uvw[3 * rowc + 1], w = a.uvw[3 * rowc + 2];
+    const double am = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
+    const double bm = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
+    const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
+    __syncthreads();
+    const int jg = a.P + a.G + j;
+    const __bf16 *Ab = (const __bf16 *)&sm.A[0];
+    const int part_stride = npairs * kAbfPerPair;
+    for (int c = 0; c < KB; ++c) {
+      if (k0 + c >= K) break;
+      const double f = a.fk[k0 + c];
+      const double S = a.d.flux64[(int64_t)jg * a.Kpad + k0 + c];
+      const double xa = am * f, xb = bm * f;
+      double pb_m1 = 0, pb_n = shp_phi0<double>(xb) * c_sc[0];
+      const double ua0 = shp_phi0<double>(xa) * c_sc[0];
+      double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+      int pbase = 0;
+      for (int ch = 0; ch <= q; ++ch) {
+        const int nb8 = min(4, (N - 32 * ch) / 8 + 1);
+        // second-axis operands of both groups: Bv[group][part][parity]
+        bf16x8 Bv[2][3][2];
+        {
+          // pkb[part][parity][hc] element jj holds orders 16 hc + 4 jj +
+          // parity (low half) and 16 hc + 4 jj + 2 + parity (high half)
+          u32x4 pkb[3][2][2];
+          double prev = pb_m1, cur = pb_n;
+#pragma unroll
+          for (int s4 = 0; s4 < 8; ++s4) {
+            const int hc = s4 >> 2, jj = s4 & 3;
+            if (s4 < 2 * nb8) {
+              double v4[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                v4[t] = cur;
+                const double nx = psi_next<double>(xb, cur, prev, c_half[32 * ch + 4 * s4 + t]);
+                prev = cur;
+                cur = nx;
+              }
+#pragma unroll
+              for (int par = 0; par < 2; ++par) {
+                const double x0 = v4[par], x1 = v4[par + 2];
+                const float2v xf = {(float)x0, (float)x1};
+                const bf16x2v h = __builtin_convertvector(xf, bf16x2v);
+                const float2v hf = __builtin_convertvector(h, float2v);
+                const float2v rf = {(float)(x0 - (double)hf[0]), (float)(x1 - (double)hf[1])};
+                const bf16x2v m = __builtin_convertvector(rf, bf16x2v);
+                pkb[0][par][hc][jj] = __builtin_bit_cast(uint32_t, h);
+                pkb[1][par][hc][jj] = __builtin_bit_cast(uint32_t, m);
+                if (CM == kCmBf16x3) {
+                  const bf16x2v l = __builtin_convertvector(rf - __builtin_convertvector(m, float2v), bf16x2v);
+                  pkb[2][par][hc][jj] = __builtin_bit_cast(uint32_t, l);
+                }
+              }
+            } else {
+#pragma unroll
+              for (int part = 0; part < 3; ++part)
+#pragma unroll
+                for (int par = 0; par < 2; ++par) pkb[part][par][hc][jj] = 0u;
+            }
+          }
+          const double rs = ch < 3 ? c_sc[ch + 1] : 1.0;
+          pb_m1 = prev * rs;
+          pb_n = cur * rs;
+          // group 0's operand: orders 0-15 of the lower half's visibility in
+          // lanes 0-31, its orders 16-31 in lanes 32-63; group 1's likewise
+          // for the upper half's visibility
+#pragma unroll
+          for (int part = 0; part < 3; ++part)
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+              u32x4 g0 = pkb[part][par][0], g1 = pkb[part][par][1];
+              if (part < parts) {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                  if (jj < 2 * nb8) {  // else both registers are zero in every lane
+                    uint32_t a0 = g0[jj], a1 = g1[jj];
+                    half_swap(a0, a1);
+                    g0[jj] = a0;
+                    g1[jj] = a1;
+                  }
+              }
+              Bv[0][part][par] = __builtin_bit_cast(bf16x8, g0);
+              Bv[1][part][par] = __builtin_bit_cast(bf16x8, g1);
+            }
+        }
+        const int nmb = q - ch + 1;
+        double prev = 0, cur = ua0;
+#pragma unroll
+        for (int mb = 0; mb < kMBMax; ++mb) {
+          if (mb >= nmb) break;
+          if (mb > 0) {  // the next block's base order
+            prev *= c_sc[mb];
+            cur *= c_sc[mb];
+          }
+          const int p = pbase + mb;
+          bf16x8 Av[3][2];  // [part][parity]
+          {
+            const int oe = p * kAbfPerPair + (tid & 63) * 8, oo = oe + 64 * 8;
+#pragma unroll
+            for (int part = 0; part < 3; ++part) {
+              const int pp = part < parts ? part : parts - 1;
+              Av[part][0] = *(const bf16x8 *)(Ab + pp * part_stride + oe);
+              Av[part][1] = *(const bf16x8 *)(Ab + pp * part_stride + oo);
+            }
+          }
+          floatx16 E0, O0, E1, O1;
+          shp_group_mfma<CM>(Av, Bv[0], E0, O0);
+          shp_group_mfma<CM>(Av, Bv[1], E1, O1);
+          // 8-row groups of this block inside the triangle
+          const int ng = min(4, (N - 32 * (ch + mb)) / 8 + 1);
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            if (g < ng) {
+              double ra[8];
+#pragma unroll
+              for (int r = 0; r < 8; ++r) {
+                ra[r] = cur;
+                const double nx = psi_next<double>(xa, cur, prev, 0.5 * (32 * mb + 8 * g + r));
+                prev = cur;
+                cur = nx;
+              }
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = 4 * g + r;
+                float e0 = E0[i], e1 = E1[i], o0 = O0[i], o1 = O1[i];
+                half_swap(e0, e1);
+                half_swap(o0, o1);
+                // rows 8 g + r (set 0) and 8 g + 4 + r (set 1), both of parity r % 2;
+                // four independent FP64 sums per part (set x row parity)
+                const int k = 2 * (r & 1);
+                if ((r & 1) == 0) {
+                  sr[k] = fma(ra[r], (double)e0, sr[k]);
+                  si[k] = fma(ra[r], (double)o0, si[k]);
+                  sr[k + 1] = fma(ra[4 + r], (double)e1, sr[k + 1]);
+                  si[k + 1] = fma(ra[4 + r], (double)o1, si[k + 1]);
+                } else {
+                  sr[k] = fma(ra[r], (double)o0, sr[k]);
+                  si[k] = fma(ra[r], (double)e0, si[k]);
+                  sr[k + 1] = fma(ra[4 + r], (double)o1, sr[k + 1]);
+                  si[k + 1] = fma(ra[4 + r], (double)e1, si[k + 1]);
+                }
+              }
+            }
+          }
+        }
+        pbase += nmb;
+      }
+      const double xr = (sr[0] + sr[1]) + (sr[2] + sr[3]), xi = (si[0] + si[1]) + (si[2] + si[3]);
+      double cs, sn;
+      turns_sincos_f64(t0 * f, cs, sn);
+      sm.acc_re[c][tid] += sgn * S * (xr * cs - xi * sn);
+      sm.acc_im[c][tid] += sgn * S * (xr * sn + xi * cs);
+    }
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    if (k0 + c >= K) break;
+    const int64_t idx = row * K + k0 + c;
+    const double re = sm.acc_re[c][tid], im = sm.acc_im[c][tid];
+    if (a.c64)
+      ((float2 *)a.vis)[idx] = make_float2((float)re, (float)(a.conj ? -im : im));
+    else
+      ((double2 *)a.vis)[idx] = make_double2(re, a.conj ? -im : im);
+  }
+}
+
+template <int CM>
 __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_shp_mfma(TileArgs a) {
   __shared__ ShpSmem<CM> sm;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  shp_tile<REC, DOT, CM>(a, tile % a.n_rb, tile / a.n_rb, sm);
+  if constexpr (CM == kCmF32)
+    shp_tile_f32(a, tile % a.n_rb, tile / a.n_rb, sm);
+  else
+    shp_tile_bf<CM>(a, tile % a.n_rb, tile / a.n_rb, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,8 +1526,8 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       pg_tile<kMixed>(job.a, rb, cb, sm.pg);
     __syncthreads();  // the tile's point/Gaussian sums are visible to the whole workgroup
     if (job.a.S > 0) {
-      shp_tile<double, double, kCmBf16x3>(job.a, rb, 2 * cb, sm.shp);
-      shp_tile<double, double, kCmBf16x3>(job.a, rb, 2 * cb + 1, sm.shp);
+      shp_tile_bf<kCmBf16x3>(job.a, rb, 2 * cb, sm.shp);
+      shp_tile_bf<kCmBf16x3>(job.a, rb, 2 * cb + 1, sm.shp);
     }
     __syncthreads();
     if (tid == 0) {
@@ -1490,17 +1651,14 @@ hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s) 
       hipLaunchKernelGGL(k_shp_fp64<true>, g, b, 0, s, a);
       break;
     case kFP32:
-      hipLaunchKernelGGL((k_shp_mfma<float, float, kCmF32>), g, b, 0, s, a);
+      hipLaunchKernelGGL(k_shp_mfma<kCmF32>, g, b, 0, s, a);
       break;
     case kMixed:
     case kMixedBf16:
-      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmBf16x3>), g, b, 0, s, a);
-      break;
-    case kMixedF32Mma:
-      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmF32>), g, b, 0, s, a);
+      hipLaunchKernelGGL(k_shp_mfma<kCmBf16x3>, g, b, 0, s, a);
       break;
     case kMixedBf16x2:
-      hipLaunchKernelGGL((k_shp_mfma<double, double, kCmBf16x2>), g, b, 0, s, a);
+      hipLaunchKernelGGL(k_shp_mfma<kCmBf16x2>, g, b, 0, s, a);
       break;
     default:
       return hipErrorNotSupported;

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libvp.so")
 
 VP_OK, VP_EINVAL, VP_ENOMEM, VP_EDEVICE, VP_EAGAIN, VP_ECAPACITY, VP_ENOTFOUND, VP_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 VP_PREC_FP64, VP_PREC_MIXED, VP_PREC_MIXED_BF16, VP_PREC_FP32, VP_PREC_MIXED_BF16X2 = 0, 1, 2, 3, 4
-VP_PREC_MIXED_F32MMA = 5
+VP_PREC_MIXED_F32MMA = 5  # retired: refused with VP_EINVAL
 VP_PREC_LUT = 6
 VP_C128, VP_C64 = 0, 1
 VP_JOB_PREDICT, VP_JOB_SUBTRACT = 0, 1
@@ -32,8 +32,7 @@ VP_NTERM_LIMIT = 8
 VP_PEEL_MAX_ANT, VP_PEEL_MAX_ITER, VP_PEEL_MAX_CG = 256, 1000, 200
 
 PRECISIONS = {"fp64": VP_PREC_FP64, "mixed": VP_PREC_MIXED, "mixed_bf16": VP_PREC_MIXED_BF16,
-              "fp32": VP_PREC_FP32, "mixed_bf16x2": VP_PREC_MIXED_BF16X2,
-              "mixed_f32mma": VP_PREC_MIXED_F32MMA, "lut": VP_PREC_LUT}
+              "fp32": VP_PREC_FP32, "mixed_bf16x2": VP_PREC_MIXED_BF16X2, "lut": VP_PREC_LUT}
 
 # every symbol declared in include/vp.h
 EXPORTS = ["vp_create_ctx", "vp_destroy_ctx", "vp_create_obs", "vp_destroy_obs", "vp_create_sky",

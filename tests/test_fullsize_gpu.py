@@ -49,7 +49,6 @@ def _predict_rows(ctx, obs, sky, prec, dtype, rows):
 @pytest.mark.parametrize("cfg,nrows_sample", [(1, 192), (2, 384)])
 @pytest.mark.parametrize("prec,dtype,tol", [(vp.VP_PREC_MIXED, vp.VP_C64, 1e-6),
                                             (vp.VP_PREC_MIXED, vp.VP_C128, 1e-6),
-                                            (vp.VP_PREC_MIXED_F32MMA, vp.VP_C128, None),
                                             (vp.VP_PREC_MIXED_BF16X2, vp.VP_C128, None),
                                             (vp.VP_PREC_FP32, vp.VP_C64, None),
                                             (vp.VP_PREC_FP64, vp.VP_C128, 1e-11)])
@@ -80,7 +79,6 @@ def fornax_full_ref():
 @pytest.mark.parametrize("prec,dtype,tol", [(vp.VP_PREC_MIXED, vp.VP_C64, 1e-6),
                                             (vp.VP_PREC_MIXED, vp.VP_C128, 1e-6),
                                             (vp.VP_PREC_FP64, vp.VP_C128, 1e-11),
-                                            (vp.VP_PREC_MIXED_F32MMA, vp.VP_C128, None),
                                             (vp.VP_PREC_MIXED_BF16X2, vp.VP_C128, None),
                                             (vp.VP_PREC_FP32, vp.VP_C64, None)])
 def test_fornax_full_output(ctx, fornax_full_ref, prec, dtype, tol):
