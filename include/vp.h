@@ -179,6 +179,28 @@ int vp_destroy_sky(vp_sky *sky); /* VP_EBUSY while a pending job uses it */
 int vp_predict(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype,
                void *vis_dev, void *hip_stream);
 
+/* vp_predict without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operation, arguments and results as vp_predict (bitwise
+ * the same output), but the per-(sky, observation) tables (direction
+ * cosines, Gaussian quadratic forms, shapelet frames, flux per component and
+ * channel) are rebuilt on every call into a fixed scratch array of
+ * 64 MiB that the library holds on each device until the process ends,
+ * instead of being allocated and cached.  Limit: 32 B per component, 32 B
+ * per Gaussian, 96 B per shapelet and 12 B per (component, channel padded to
+ * a multiple of 8), each part rounded up to 256 B, at most 64 MiB in all
+ * (e.g. 20,000 components x 32 channels fit; 5,000 components x 1,024
+ * channels fit; 100,000 components x 384 channels do not); a larger pair is
+ * refused with VP_EINVAL.  VP_PREC_LUT is refused (its table is per context).
+ * No hipMalloc, hipFree, event or other allocating call is made.  Every call
+ * on one device uses that device's single array, which keeps the last call's
+ * tables: calls that overlap on one device (on different streams, or from
+ * different threads without ordering) race and give wrong results; calls
+ * ordered on one stream do not.  The sky, observation and context must have
+ * been created beforehand (those calls allocate).  Errors as vp_predict. */
+int vp_predict_noalloc(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype,
+                       void *vis_dev, void *hip_stream);
+
 /* Subtract (peel with unit gains): data <- data - V, in place on caller-owned
  * device memory laid out as for vp_predict.  Same errors. */
 int vp_subtract(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype,

@@ -718,6 +718,46 @@ int vp_predict(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision,
   return run_tiles(ctx, sky, obs, precision, dtype, vis_dev, 0, (hipStream_t)hip_stream);
 }
 
+int vp_predict_noalloc(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis_dev,
+                       void *hip_stream) {
+  int rc = check_call(ctx, sky, obs, precision, dtype, vis_dev);
+  if (rc != VP_OK) return rc;
+  if (precision == VP_PREC_LUT)
+    return set_error(VP_EINVAL, "vp_predict_noalloc: the lookup-table variant needs a per-context table");
+  // the pair's tables, laid out in the device's scratch array (256-byte aligned parts)
+  const int J = sky->P + sky->G + sky->S;
+  const uint64_t Jc = (uint64_t)std::max(J, 1), Gc = (uint64_t)std::max(sky->G, 1);
+  const uint64_t Sc = (uint64_t)std::max(sky->S, 1), Kp = (uint64_t)obs->Kpad;
+  auto up = [](uint64_t b) { return (b + 255) & ~(uint64_t)255; };
+  const uint64_t o_gq = up(sizeof(double4) * Jc);
+  const uint64_t o_sf = o_gq + up(sizeof(double4) * Gc);
+  const uint64_t o_f32 = o_sf + up(sizeof(double) * 12 * Sc);
+  const uint64_t o_f64 = o_f32 + up(sizeof(float) * Jc * Kp);
+  const uint64_t need = o_f64 + up(sizeof(double) * Jc * Kp);
+  if (need > kNoAllocScratchBytes)
+    return set_error(VP_EINVAL,
+                     "vp_predict_noalloc: %d components x %d padded channels need %llu bytes of tables; "
+                     "the scratch holds %llu",
+                     J, obs->Kpad, (unsigned long long)need, (unsigned long long)kNoAllocScratchBytes);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return set_error(VP_EDEVICE, "cannot select device %d", ctx->device);
+  char *base = (char *)noalloc_scratch(ctx->device);
+  if (!base) return set_error(VP_EDEVICE, "no scratch address for device %d", ctx->device);
+  Derived d;
+  d.pos = (double4 *)base;
+  d.gq = (double4 *)(base + o_gq);
+  d.sframe = (double *)(base + o_sf);
+  d.flux32 = (float *)(base + o_f32);
+  d.flux64 = (double *)(base + o_f64);
+  const hipStream_t stream = (hipStream_t)hip_stream;
+  // every entry the tile kernels read is written here first (the flux table
+  // includes its zero padding), so nothing is cleared
+  hipError_t e = launch_derive(make_derive_args(sky, obs, d), stream);
+  if (e == hipSuccess) e = launch_flux(make_flux_args(sky, obs, d), stream);
+  if (e != hipSuccess) return hip_error(e, "building the tables in the scratch array");
+  return launch_passes(nullptr, sky, obs, precision, dtype, vis_dev, 0, stream, d, nullptr);
+}
+
 int vp_subtract(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *data_dev,
                 void *hip_stream) {
   int rc = check_call(ctx, sky, obs, precision, dtype, data_dev);

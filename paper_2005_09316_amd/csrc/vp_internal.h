@@ -191,6 +191,11 @@ struct GainArgs {
 // and process (the device must be current).
 constexpr int kMaxDevices = 64;
 hipError_t device_init(int dev);
+// Device address of this device's no-allocation scratch array (valid after
+// device_init(dev) succeeded), or null.
+void *noalloc_scratch(int dev);
+// Size of that array: per-(sky, observation) tables of vp_predict_noalloc.
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
 
 // Host-side launchers (vp_kernels.hip).
 hipError_t launch_derive(const DeriveArgs &a, hipStream_t s);

@@ -1570,13 +1570,31 @@ static hipError_t init_constants() {
   return e;
 }
 
+// Scratch of vp_predict_noalloc (the per-(sky, observation) tables of one
+// call), one array per device for the life of the process.  In host code the
+// name is only a stand-in: its device address, which differs per device, is
+// looked up once per device below and used everywhere instead.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static void *g_scratch[kMaxDevices];
+
 hipError_t device_init(int dev) {
   if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
   std::call_once(g_init_once[dev], [dev]() {
     // the caller has made `dev` current
-    g_init_err[dev] = init_constants();
+    hipError_t e = init_constants();
+    if (e == hipSuccess) {
+      void *p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e == hipSuccess) g_scratch[dev] = p;
+    }
+    g_init_err[dev] = e;
   });
   return g_init_err[dev];
+}
+
+void *noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices || device_init(dev) != hipSuccess) return nullptr;
+  return g_scratch[dev];
 }
 
 static hipError_t upload_tables() {

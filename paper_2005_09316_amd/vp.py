@@ -36,7 +36,7 @@ PRECISIONS = {"fp64": VP_PREC_FP64, "mixed": VP_PREC_MIXED, "mixed_bf16": VP_PRE
 
 # every symbol declared in include/vp.h
 EXPORTS = ["vp_create_ctx", "vp_destroy_ctx", "vp_create_obs", "vp_destroy_obs", "vp_create_sky",
-           "vp_destroy_sky", "vp_predict", "vp_subtract", "vp_peel", "vp_submit", "vp_poll", "vp_job_footprint",
+           "vp_destroy_sky", "vp_predict", "vp_predict_noalloc", "vp_subtract", "vp_peel", "vp_submit", "vp_poll", "vp_job_footprint",
            "vp_profile", "vp_profile_read", "vp_last_error", "vp_version"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
         "vp_create_sky": ([vp, ctypes.POINTER(vp_sky_desc), ctypes.POINTER(vp)], ctypes.c_int),
         "vp_destroy_sky": ([vp], ctypes.c_int),
         "vp_predict": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
+        "vp_predict_noalloc": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
         "vp_subtract": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
         "vp_peel": ([vp, vp, vp, _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int, vp, vp,
                      vp], ctypes.c_int),
@@ -204,6 +205,10 @@ def vp_destroy_sky(sky: int):
 
 def vp_predict(ctx: int, sky: int, obs: int, precision: int, dtype: int, vis_dev: int, hip_stream: int = 0):
     _check(load().vp_predict(ctx, sky, obs, int(precision), int(dtype), vis_dev, hip_stream or None))
+
+
+def vp_predict_noalloc(ctx: int, sky: int, obs: int, precision: int, dtype: int, vis_dev: int, hip_stream: int = 0):
+    _check(load().vp_predict_noalloc(ctx, sky, obs, int(precision), int(dtype), vis_dev, hip_stream or None))
 
 
 def vp_subtract(ctx: int, sky: int, obs: int, precision: int, dtype: int, data_dev: int, hip_stream: int = 0):

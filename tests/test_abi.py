@@ -49,6 +49,7 @@ def test_null_arguments_are_rejected_before_any_device_work():
     assert lib.vp_create_obs(None, None, None) == vp.VP_EINVAL
     assert lib.vp_create_sky(None, None, None) == vp.VP_EINVAL
     assert lib.vp_predict(None, None, None, 1, 1, None, None) == vp.VP_EINVAL
+    assert lib.vp_predict_noalloc(None, None, None, 1, 1, None, None) == vp.VP_EINVAL
     assert "NULL" in vp.vp_last_error()
 
 
