@@ -60,32 +60,6 @@ __device__ __forceinline__ double2 load_vis(const void *p, int c64, int64_t i) {
   return ((const double2 *)p)[i];
 }
 
-// Removes from v (tile k's entry of a vector over tiles) its part along the
-// gauge direction i g of k's connected component:
-//   v <- v - i g_k (sum_{o in C} Im(g_o^* v_o)) / (sum_{o in C} |g_o|^2).
-// Sums run over the tiles in index order (deterministic); pv is LDS scratch.
-__device__ __forceinline__ double2 gauge_project(double2 v, double2 gk, int k, int ck, bool own, int n,
-                                                 const int *comp, const double2 *g, double *pv) {
-  if (own) pv[k] = ck >= 0 ? gk.x * v.y - gk.y * v.x : 0.0;
-  __syncthreads();
-  if (own && ck >= 0) {
-    double num = 0.0, den = 0.0;
-    for (int o = 0; o < n; ++o) {
-      if (comp[o] != ck) continue;
-      const double2 go = g[o];
-      num += pv[o];
-      den += go.x * go.x + go.y * go.y;
-    }
-    if (den > 0.0) {
-      const double c = num / den;
-      v.x += c * gk.y;
-      v.y -= c * gk.x;
-    }
-  }
-  __syncthreads();
-  return v;
-}
-
 // Table element types: TT (FP64 or FP32) and its complex pair.
 template <typename TT>
 struct TabPair;
@@ -182,6 +156,74 @@ __device__ __forceinline__ double2 block_sum2(double u, double v, double2 *red) 
   return s;
 }
 
+// Sums of three values over the workgroup, as block_sum2; red holds 2 NT / 64
+// pairs.
+template <int NT>
+__device__ __forceinline__ double3 block_sum3(double u, double v, double w, double2 *red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    u += __shfl_xor(u, o);
+    v += __shfl_xor(v, o);
+    w += __shfl_xor(w, o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[2 * wave] = make_double2(u, v);
+    red[2 * wave + 1] = make_double2(w, 0.0);
+  }
+  __syncthreads();
+  double3 s = make_double3(0.0, 0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) {
+    s.x += red[2 * q].x;
+    s.y += red[2 * q].y;
+    s.z += red[2 * q + 1].x;
+  }
+  return s;
+}
+
+// Removes from v (tile k's entry of a vector over tiles) its part along the
+// gauge direction i g of k's connected component:
+//   v <- v - i g_k (sum_{o in C} Im(g_o^* v_o)) / (sum_{o in C} |g_o|^2).
+// With every used tile in one component (single) the two sums are workgroup
+// reductions through redp (NT / 64 pairs); otherwise each tile's sums run
+// over the tiles of its component in index order, pv being LDS scratch.
+// Deterministic either way.
+template <int NT>
+__device__ __forceinline__ double2 gauge_project(double2 v, double2 gk, int k, int ck, bool own, int n,
+                                                 const int *comp, const double2 *g, double *pv, bool single,
+                                                 double2 *redp) {
+  if (single) {
+    const bool in = own && ck >= 0;
+    const double2 s = block_sum2<NT>(in ? gk.x * v.y - gk.y * v.x : 0.0, in ? gk.x * gk.x + gk.y * gk.y : 0.0, redp);
+    if (in && s.y > 0.0) {
+      const double c = s.x / s.y;
+      v.x += c * gk.y;
+      v.y -= c * gk.x;
+    }
+    __syncthreads();  // redp's reads end before its next writes
+    return v;
+  }
+  if (own) pv[k] = ck >= 0 ? gk.x * v.y - gk.y * v.x : 0.0;
+  __syncthreads();
+  if (own && ck >= 0) {
+    double num = 0.0, den = 0.0;
+    for (int o = 0; o < n; ++o) {
+      if (comp[o] != ck) continue;
+      const double2 go = g[o];
+      num += pv[o];
+      den += go.x * go.x + go.y * go.y;
+    }
+    if (den > 0.0) {
+      const double c = num / den;
+      v.x += c * gk.y;
+      v.y -= c * gk.x;
+    }
+  }
+  __syncthreads();
+  return v;
+}
+
 // Index of (i, j) in W packed with its (zero) diagonal: rows i of the upper
 // triangle j >= i, one after another.
 __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
@@ -206,12 +248,13 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
   double2 *y = g + kPeelMaxAnt;                   // [kPeelMaxAnt] g_o p_o^* of the current direction
+  float2 *y32 = (float2 *)y;                      // the same, FP32, for the FP32 operator (FP32 tables)
   double2 *pa = y + kPeelMaxAnt;                  // [NT] partial sums
   double *pv = (double *)(pa + NT);               // [kPeelMaxAnt] projection scratch
   int *comp = (int *)(pv + kPeelMaxAnt);          // [kPeelMaxAnt] connected component of each tile
-  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [2][NT / 64] reduction scratch, used alternately
-  double2 *red2 = red + NT / 64;
-  WT *W = (WT *)(red2 + NT / 64);                 // [n (n + 1) / 2] |I|^2, packed with the diagonal
+  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [2 NT / 64] reduction scratch
+  double2 *redp = red + 2 * (NT / 64);            // [NT / 64] reduction scratch of the projections
+  WT *W = (WT *)(redp + NT / 64);                 // [n (n + 1) / 2] |I|^2, packed with the diagonal
 
   const int cl = blockIdx.x, cell = a.cell0 + cl;
   const int t = cell / a.K, kc = cell % a.K;
@@ -248,7 +291,40 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   }
   __syncthreads();
 
-  // sum over this part's o of W_ko v_o (v in LDS); the diagonal term is zero
+  // sum over this part's o of W_ko v_o (v in LDS), FP32 products and sums:
+  // the step's operator on the mixed path, whose W is FP32 already; the
+  // diagonal term is zero
+  auto wdot32 = [&](const float2 *v) {
+    float2 acc = make_float2(0.f, 0.f);
+    auto add = [&](int p, int o) {
+      const float wv = (float)W[p];
+      const float2 vo = v[o];
+      acc.x = fmaf(wv, vo.x, acc.x);
+      acc.y = fmaf(wv, vo.y, acc.y);
+    };
+    for (int c = 0; 64 * c < n; ++c) {
+      const int oa = min(n, 64 * c + sa), ob = min(n, 64 * c + sb);
+      int L = oa * n - oa * (oa + 1) / 2;
+      if (c < wb) {
+#pragma unroll 4
+        for (int o = oa; o < ob; ++o) {
+          add(L + kr, o);
+          L += n - o - 1;
+        }
+      } else if (c > wb) {
+#pragma unroll 4
+        for (int o = oa; o < ob; ++o) add(U + o, o);
+      } else {
+#pragma unroll 4
+        for (int o = oa; o < ob; ++o) {
+          add(o < kr ? L + kr : U + o, o);
+          L += n - o - 1;
+        }
+      }
+    }
+    return make_double2(acc.x, acc.y);
+  };
+  // the same in FP64 (v FP64), or the sum of W_ko |v_o|^2 (sq)
   auto wdot = [&](const double2 *v, bool sq) {
     double2 acc = make_double2(0.0, 0.0);
     auto add = [&](int p, int o) {
@@ -333,54 +409,278 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
       scale += sqrt(gk.x * gk.x + gk.y * gk.y) * D;
     }
     const double minv = Dt > 0.0 ? 1.0 / Dt : 0.0;
-    r = gauge_project(r, gk, k, ck, own, n, comp, g, pv);
-    // below this |r|^2 the right-hand side is rounding noise: no step
+    r = gauge_project<NT>(r, gk, k, ck, own, n, comp, g, pv, a.single_comp, redp);
+    // Preconditioned conjugate gradients in the Chronopoulos-Gear form: per
+    // step one operator application w = A u to the preconditioned residual u
+    // and one workgroup reduction of gamma = (res, u), delta = (u, w) and
+    // |res|^2 together (two barriers a step); the direction's image s = A p
+    // follows from s = w + beta s, and (p, A p) = delta - beta gamma / alpha.
+    // The inner product is the real one, sum_k Re(a_k^* b_k), for which the
+    // operator is self-adjoint.  delta's W part, sum_k Re(u_k^* g_k S_k) with
+    // S_k = sum_o W_ko y_o and y_o = g_o u_o^*, equals sum_k Re(y_k S_k): each
+    // (tile, part) thread adds the share of its part of the sum.
     double2 x = make_double2(0.0, 0.0), res = r;
-    double2 z = make_double2(minv * r.x, minv * r.y), pdir = z;
     const double2 s0 = block_sum2<NT>(res.x * res.x + res.y * res.y, scale * scale, red);
+    // below this |r|^2 the right-hand side is rounding noise: no step
     const double floor2 = kGainFloor * kGainFloor * s0.y;
-    double rr = s0.x, rz = block_sum2<NT>(res.x * z.x + res.y * z.y, 0.0, red2).x;
-    const double rr0 = rr;
+    const double rr0 = s0.x;
+    double2 u = make_double2(minv * res.x, minv * res.y);
+    double2 pdir = make_double2(0.0, 0.0), sdir = make_double2(0.0, 0.0);
+    double gam_old = 1.0, alpha_old = 1.0;
     int steps = 0;  // workgroup-uniform: every stopping test uses block sums
     for (int cg = 0; cg < a.max_cg; ++cg) {
-      if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2) || !(rz > 0.0)) break;
-      if (own) y[k] = cmul(gk, cconj(pdir));
-      __syncthreads();
-      pa[tid] = wdot(y, false);
-      __syncthreads();
-      double2 q = make_double2(0.0, 0.0);
       if (own) {
-        double2 s = make_double2(0.0, 0.0);
+        const double2 yk = cmul(gk, cconj(u));
+        if constexpr (tab64)
+          y[k] = yk;
+        else
+          y32[k] = make_float2((float)yk.x, (float)yk.y);
+      }
+      __syncthreads();
+      double2 sp;
+      double2 yr;
+      if constexpr (tab64) {
+        sp = wdot(y, false);
+        yr = y[kr];
+      } else {
+        sp = wdot32(y32);
+        yr = make_double2(y32[kr].x, y32[kr].y);
+      }
+      double dterm = row ? yr.x * sp.x - yr.y * sp.y : 0.0, gterm = 0.0, rterm = 0.0;
+      if (own) {
+        dterm += Dt * (u.x * u.x + u.y * u.y);
+        gterm = res.x * u.x + res.y * u.y;
+        rterm = res.x * res.x + res.y * res.y;
+      }
+      pa[tid] = sp;
+      const double3 sums = block_sum3<NT>(gterm, dterm, rterm, red);  // its barrier also publishes pa
+      const double gam = sums.x, delta = sums.y, rr = sums.z;
+      if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2) || !(gam > 0.0)) break;
+      const double beta = cg > 0 ? gam / gam_old : 0.0;
+      const double eta = delta - beta * gam / alpha_old;
+      if (!(eta > 0.0)) break;
+      const double alpha = gam / eta;
+      if (own) {
+        double2 sw = make_double2(0.0, 0.0);
         for (int j = 0; j < parts; ++j) {
           const double2 v = pa[j * nk + k];
-          s.x += v.x;
-          s.y += v.y;
+          sw.x += v.x;
+          sw.y += v.y;
         }
-        const double2 gs = cmul(gk, s);
-        q = make_double2(Dt * pdir.x + gs.x, Dt * pdir.y + gs.y);
+        const double2 gs = cmul(gk, sw);
+        const double2 w = make_double2(Dt * u.x + gs.x, Dt * u.y + gs.y);
+        pdir = make_double2(u.x + beta * pdir.x, u.y + beta * pdir.y);
+        sdir = make_double2(w.x + beta * sdir.x, w.y + beta * sdir.y);
+        x.x += alpha * pdir.x;
+        x.y += alpha * pdir.y;
+        res.x -= alpha * sdir.x;
+        res.y -= alpha * sdir.y;
+        u = make_double2(minv * res.x, minv * res.y);
       }
-      const double pq = block_sum2<NT>(pdir.x * q.x + pdir.y * q.y, 0.0, red).x;
-      if (!(pq > 0.0)) break;
-      const double alpha = rz / pq;
-      x.x += alpha * pdir.x;
-      x.y += alpha * pdir.y;
-      res.x -= alpha * q.x;
-      res.y -= alpha * q.y;
-      z = make_double2(minv * res.x, minv * res.y);
-      const double2 s1 = block_sum2<NT>(res.x * res.x + res.y * res.y, res.x * z.x + res.y * z.y, red2);
-      const double beta = s1.y / rz;
-      pdir = make_double2(z.x + beta * pdir.x, z.y + beta * pdir.y);
-      rr = s1.x;
-      rz = s1.y;
+      gam_old = gam;
+      alpha_old = alpha;
       ++steps;
     }
-    x = gauge_project(x, gk, k, ck, own, n, comp, g, pv);
+    x = gauge_project<NT>(x, gk, k, ck, own, n, comp, g, pv, a.single_comp, redp);
     gk.x += x.x;
     gk.y += x.y;
     if (own) g[k] = gk;
     __syncthreads();
     // no step taken: the gains did not change, so every further iteration
     // would repeat this one exactly
+    if (steps == 0) break;
+  }
+
+  if (own) {
+    if (a.gains) a.gains[(int64_t)cell * n + k] = gk;
+    a.gw[((int64_t)t * n + k) * a.K + kc] = gk;
+  }
+}
+
+// The mixed path's solve for large arrays (up to kPeelMaxAnt tiles), with W
+// held in registers instead of LDS.  One workgroup of 64 NW threads per cell.
+// Wave w takes the columns o of [w OPW, (w + 1) OPW) and lane l the rows
+// k = l + 64 j (j < RPL), so that each thread holds the RPL x OPW block of W
+// (FP32) it multiplies: each broadcast read of the direction's y_o from LDS
+// serves RPL rows, and W is never read from LDS.  The partial sums of the
+// NW column blocks meet in LDS; thread k (k < n, the first n threads) owns
+// tile k's gain and conjugate-gradient state.  Same iteration, stopping rules
+// and arithmetic as k_gain_solve's mixed path (FP32 operator, FP64 sums and
+// state), with D_k summed from the same FP32 W.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_gain_solve_rw(GainArgs a) {
+  constexpr int NT = 64 * NW, RPL = kPeelMaxAnt / 64, OPW = kPeelMaxAnt / NW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
+  float2 *y32 = (float2 *)(g + kPeelMaxAnt);      // [kPeelMaxAnt] g_o u_o^* of the current direction
+  double2 *pa = (double2 *)(y32 + kPeelMaxAnt);   // [NW][kPeelMaxAnt] column-block partial sums
+  float2 *pa32 = (float2 *)pa;                    // the same buffer for the FP32 operator's partials
+  double *pv = (double *)(pa + NW * kPeelMaxAnt); // [kPeelMaxAnt] projection scratch
+  int *comp = (int *)(pv + kPeelMaxAnt);          // [kPeelMaxAnt] connected component of each tile
+  double2 *red = (double2 *)(comp + kPeelMaxAnt); // [2 NT / 64] reduction scratch
+  double2 *redp = red + 2 * (NT / 64);            // [NT / 64] reduction scratch of the projections
+
+  const int cl = blockIdx.x, cell = a.cell0 + cl;
+  const int t = cell / a.K, kc = cell % a.K;
+  const int n = a.n_ant, tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ob = wv * OPW, on = max(0, min(OPW, n - ob));  // this wave's columns (wave-uniform)
+  const bool own = tid < n;
+  const int k = own ? tid : 0;
+
+  const float2 *X = (const float2 *)a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
+  const float *Wf = (const float *)a.wf + (int64_t)cl * n * n;    // |I|^2 [o n + k], zero for o == k
+  float Wr[RPL][OPW];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const int kj = lane + 64 * j;
+#pragma unroll
+    for (int i = 0; i < OPW; ++i) Wr[j][i] = (kj < n && i < on) ? Wf[(int64_t)(ob + i) * n + kj] : 0.f;
+  }
+  double2 gk = make_double2(1.0, 0.0);
+  const int ck = own ? a.comp[k] : -1;
+  if (own) {
+    g[k] = gk;
+    comp[k] = ck;
+  }
+  // the gains' and the direction's entries past n stay zero, so that the
+  // products with the register copy of W (zero there too) need no bounds
+  for (int i = tid; i < kPeelMaxAnt; i += NT) {
+    y32[i] = make_float2(0.f, 0.f);
+    if (i >= n) g[i] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+
+  for (int it = 0; it < a.n_iter; ++it) {
+    // r_k = sum_o g_o X_ko - g_k D_k, D_k = sum_o W_ko |g_o|^2 (W from the
+    // table: the same FP32 values as the registers); sa: sum of |g_o X_ko|,
+    // for the rounding level of r_k.  One row of this lane at a time, so that
+    // the register copy of W stays the only large live state.
+    double2 sx[RPL];
+    double sd[RPL], sa[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const int kj = lane + 64 * j;
+      double2 ax = make_double2(0.0, 0.0);
+      double ad = 0.0, aa = 0.0;
+      if (kj < n) {
+#pragma unroll 4
+        for (int i = 0; i < on; ++i) {
+          const int o = ob + i;
+          const double2 go = g[o];
+          const double g2 = go.x * go.x + go.y * go.y;
+          const float2 xt = X[(int64_t)o * n + kj];
+          const double2 xv = make_double2(xt.x, xt.y);
+          ax.x += go.x * xv.x - go.y * xv.y;
+          ax.y += go.x * xv.y + go.y * xv.x;
+          aa += (double)__builtin_amdgcn_sqrtf((float)(g2 * (xv.x * xv.x + xv.y * xv.y)));
+          ad += g2 * (double)Wf[(int64_t)o * n + kj];
+        }
+      }
+      sx[j] = ax;
+      sd[j] = ad;
+      sa[j] = aa;
+    }
+    // two rounds through the partial-sum buffer: (sx), (sd, sa)
+    double2 r = make_double2(0.0, 0.0);
+    double Dt = 0.0, scale = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+      if (lane + 64 * j < n) pa[wv * kPeelMaxAnt + lane + 64 * j] = sx[j];
+    __syncthreads();
+    if (own)
+      for (int w = 0; w < NW; ++w) {
+        r.x += pa[w * kPeelMaxAnt + k].x;
+        r.y += pa[w * kPeelMaxAnt + k].y;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+      if (lane + 64 * j < n) pa[wv * kPeelMaxAnt + lane + 64 * j] = make_double2(sd[j], sa[j]);
+    __syncthreads();
+    if (own) {
+      for (int w = 0; w < NW; ++w) {
+        Dt += pa[w * kPeelMaxAnt + k].x;
+        scale += pa[w * kPeelMaxAnt + k].y;
+      }
+      r.x -= gk.x * Dt;
+      r.y -= gk.y * Dt;
+      scale += sqrt(gk.x * gk.x + gk.y * gk.y) * Dt;
+    }
+    const double minv = Dt > 0.0 ? 1.0 / Dt : 0.0;
+    r = gauge_project<NT>(r, gk, k, ck, own, n, comp, g, pv, a.single_comp, redp);
+    // conjugate gradients in the Chronopoulos-Gear form, as in k_gain_solve
+    double2 x = make_double2(0.0, 0.0), res = r;
+    const double2 s0 = block_sum2<NT>(res.x * res.x + res.y * res.y, scale * scale, red);
+    const double floor2 = kGainFloor * kGainFloor * s0.y;
+    const double rr0 = s0.x;
+    double2 u = make_double2(minv * res.x, minv * res.y);
+    double2 pdir = make_double2(0.0, 0.0), sdir = make_double2(0.0, 0.0);
+    double gam_old = 1.0, alpha_old = 1.0;
+    int steps = 0;
+    for (int cg = 0; cg < a.max_cg; ++cg) {
+      if (own) {
+        const double2 yk = cmul(gk, cconj(u));
+        y32[k] = make_float2((float)yk.x, (float)yk.y);
+      }
+      __syncthreads();
+      float2 acc[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) acc[j] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < OPW; ++i) {
+        const float2 yo = y32[ob + i];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          acc[j].x = fmaf(Wr[j][i], yo.x, acc[j].x);
+          acc[j].y = fmaf(Wr[j][i], yo.y, acc[j].y);
+        }
+      }
+      double dterm = 0.0, gterm = 0.0, rterm = 0.0;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {  // rows past n: zero products and a zero direction entry
+        const float2 yj = y32[lane + 64 * j];
+        dterm += (double)yj.x * acc[j].x - (double)yj.y * acc[j].y;
+        pa32[wv * kPeelMaxAnt + lane + 64 * j] = acc[j];
+      }
+      if (own) {
+        dterm += Dt * (u.x * u.x + u.y * u.y);
+        gterm = res.x * u.x + res.y * u.y;
+        rterm = res.x * res.x + res.y * res.y;
+      }
+      const double3 sums = block_sum3<NT>(gterm, dterm, rterm, red);  // its barrier also publishes pa32
+      const double gam = sums.x, delta = sums.y, rr = sums.z;
+      if (!(rr > a.cg_tol2 * rr0) || !(rr > floor2) || !(gam > 0.0)) break;
+      const double beta = cg > 0 ? gam / gam_old : 0.0;
+      const double eta = delta - beta * gam / alpha_old;
+      if (!(eta > 0.0)) break;
+      const double alpha = gam / eta;
+      if (own) {
+        double2 sw = make_double2(0.0, 0.0);
+        for (int w = 0; w < NW; ++w) {
+          const float2 v = pa32[w * kPeelMaxAnt + k];
+          sw.x += v.x;
+          sw.y += v.y;
+        }
+        const double2 gs = cmul(gk, sw);
+        const double2 wk = make_double2(Dt * u.x + gs.x, Dt * u.y + gs.y);
+        pdir = make_double2(u.x + beta * pdir.x, u.y + beta * pdir.y);
+        sdir = make_double2(wk.x + beta * sdir.x, wk.y + beta * sdir.y);
+        x.x += alpha * pdir.x;
+        x.y += alpha * pdir.y;
+        res.x -= alpha * sdir.x;
+        res.y -= alpha * sdir.y;
+        u = make_double2(minv * res.x, minv * res.y);
+      }
+      gam_old = gam;
+      alpha_old = alpha;
+      ++steps;
+    }
+    x = gauge_project<NT>(x, gk, k, ck, own, n, comp, g, pv, a.single_comp, redp);
+    gk.x += x.x;
+    gk.y += x.y;
+    if (own) g[k] = gk;
+    __syncthreads();
     if (steps == 0) break;
   }
 
@@ -416,7 +716,7 @@ __global__ __launch_bounds__(256) void k_gain_subtract(GainArgs a) {
 size_t gain_smem_bytes(int n_ant, bool w64, int threads) {
   const size_t packed = (size_t)n_ant * (n_ant + 1) / 2;
   return kPeelMaxAnt * (2 * sizeof(double2) + sizeof(double) + sizeof(int)) + threads * sizeof(double2) +
-         2 * (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));
+         3 * (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));  // red, redp
 }
 
 template <typename WT, int NT, typename TT>
@@ -450,6 +750,13 @@ hipError_t launch_gain_subtract(const GainArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+constexpr int kRwWaves = 8;  // waves per cell of k_gain_solve_rw
+
+size_t gain_rw_smem_bytes() {
+  return kPeelMaxAnt * (sizeof(double2) + sizeof(float2) + kRwWaves * sizeof(double2) + sizeof(double) + sizeof(int)) +
+         3 * kRwWaves * sizeof(double2);
+}
+
 size_t gain_cell_bytes(int n_ant, bool w32) {
   return (size_t)n_ant * n_ant * (w32 ? sizeof(float2) + sizeof(float) : sizeof(double2) + sizeof(double));
 }
@@ -467,8 +774,13 @@ hipError_t launch_gain(const GainArgs &a, hipStream_t s) {
   if (a.w32) {
     if (3 * gain_smem_bytes(a.n_ant, false, 256) <= kPeelSmemMax) return launch_solve<float, 256, float>(a, s);
     if (2 * gain_smem_bytes(a.n_ant, false, 512) <= kPeelSmemMax) return launch_solve<float, 512, float>(a, s);
-    if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024, float>(a, s);
-    return launch_solve<float, 1024, float>(a, s);
+    // larger arrays: W in registers (one cell per CU either way, but no LDS
+    // traffic for W and a quarter of the broadcast reads)
+    const size_t sm = gain_rw_smem_bytes();
+    e = hipFuncSetAttribute((const void *)k_gain_solve_rw<kRwWaves>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gain_solve_rw<kRwWaves>, dim3((unsigned)a.ncell), dim3(64 * kRwWaves), sm, s, a);
+    return hipGetLastError();
   }
   if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024, double>(a, s);
   return launch_solve<float, 1024, double>(a, s);

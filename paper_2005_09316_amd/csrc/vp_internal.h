@@ -185,6 +185,7 @@ struct GainArgs {
   void *xt;               // workspace [ncell][n_ant][n_ant] complex X (float2 when w32, else double2)
   void *wf;               // workspace [ncell][n_ant][n_ant] |I|^2 (float when w32, else double)
   int w32;                // 1 (mixed path): FP32 tables and FP32 W in the step's operator, FP64 sums
+  int single_comp;        // 1: every tile with a baseline is in one connected component
 };
 
 // Device set-up (vp_kernels.hip): the recurrence constants, once per device

@@ -41,6 +41,7 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
     tab[b] = i;
     tab[(size_t)B + b] = j;
   }
+  bool single = true;  // every tile with a baseline in one component
   {
     // union-find over the baselines; a component is named by its root tile
     std::vector<int32_t> up(n_ant);
@@ -57,6 +58,8 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
     }
     int32_t *comp = tab.data() + 2 * (size_t)B + npairs;
     for (int k = 0; k < n_ant; ++k) comp[k] = used[k] ? root(k) : -1;
+    for (int k = 0; k < n_ant; ++k)
+      if (comp[k] >= 0 && comp[k] != root(ant1[0])) single = false;
   }
   if (!gain_supported(n_ant)) return set_error(VP_EINVAL, "%d tiles not supported by the gain solve", n_ant);
   DeviceGuard g(ctx->device);
@@ -111,7 +114,12 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   a.n_ant = n_ant;
   a.n_iter = n_iter;
   a.max_cg = VP_PEEL_MAX_CG;
-  a.cg_tol2 = 1e-24;
+  // relative residual at which a step's conjugate-gradient solve stops: 1e-12
+  // with FP64 tables and operator; 1e-6 on the mixed path, whose operator
+  // (FP32 W and FP32 products) is itself accurate to ~1e-7 only, so that
+  // iterating further refines nothing (the Gauss-Newton fixed point is set by
+  // the right-hand side, which keeps its FP64 sums)
+  a.cg_tol2 = w32 ? 1e-12 : 1e-24;
   a.model = w.model;
   a.data = data_dev;
   a.c64 = dtype == VP_C64;
@@ -122,6 +130,7 @@ int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *an
   a.gains = (double2 *)gains_dev;
   a.gw = (double2 *)w.gw;
   a.w32 = w32;
+  a.single_comp = single ? 1 : 0;
   a.xt = w.ws;
   a.wf = (char *)w.ws + (size_t)chunk * n_ant * n_ant * (w32 ? sizeof(float2) : sizeof(double2));
   {
