@@ -20,15 +20,17 @@
 // The solve also stops once the residual is at the rounding level of r.
 // With X_ko = I^* V seen from tile k (a per-cell table built once), the
 // right-hand side is r_k = sum_o g_o X_ko - g_k D_k; X streams from HBM once
-// per Gauss-Newton iteration as a full n x n table, coalesced over k.  For
-// the conjugate-gradient products W sits in LDS, packed.  On the FP64 path
-// the tables are FP64, D_k is summed from the FP64 W table, and W in LDS is
-// FP64 while it fits (up to 183 tiles) and FP32 beyond: that changes the
-// step's operator at the 1e-7 level, not the right-hand side, so not the
-// fixed point.  On the mixed path the tables hold X and W rounded to FP32
-// (sums and steps stay FP64) and D_k comes from the LDS copy of W: the
-// solution moves by the tables' rounding, ~1e-7 relative, and the
-// right-hand side pass reads 8 bytes per tile pair instead of 24.
+// per Gauss-Newton iteration as a full n x n table, coalesced over k.  The
+// conjugate gradients take one operator application and one workgroup
+// reduction per step (Chronopoulos-Gear form).  On the FP64 path the tables
+// are FP64, D_k is summed from the FP64 W table, and the operator's W sits
+// in LDS, packed, FP64 while it fits (up to 183 tiles) and FP32 beyond: that
+// changes the step's operator at the 1e-7 level, not the right-hand side, so
+// not the fixed point.  On the mixed path the tables hold X and W rounded to
+// FP32 (sums and steps stay FP64, so the solution moves by the tables'
+// rounding, ~1e-7 relative), each thread holds its block of W in registers,
+// the operator's products are FP32 (its W is FP32 already) and each step's
+// solve stops at a relative residual of 1e-6 instead of 1e-12.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -230,25 +232,22 @@ __device__ __forceinline__ int packed_index(int n, int i, int j) {  // i <= j
   return i * n - i * (i - 1) / 2 + (j - i);
 }
 
-// One workgroup of NT threads per cell.  Thread (k, part) with
-// k = tid mod nk (nk = n rounded up to 64) and part = tid / nk sums over a
-// wave-uniform share of the other tiles (the part-th slice o0 <= o < o1 for
-// the right-hand side, the part-th share of every 64-tile block for the W
-// products); the part-0 thread of tile k holds the tile's gain and its
-// conjugate-gradient state; threads with part >= NT / nk (when nk does not
-// divide NT) take no share.  W sits in LDS packed with its zero diagonal, as WT.  The operator of the
-// step uses these W values for its diagonal too, so that i g stays its
-// exact null vector; the right-hand side uses the tables (TT), and with
-// FP32 tables that same LDS copy of W for D.  The solve is conjugate
-// gradients preconditioned by that diagonal (Jacobi).
-template <typename WT, int NT, typename TT>
+// The FP64 path's solve.  One workgroup of NT threads per cell.  Thread
+// (k, part) with k = tid mod nk (nk = n rounded up to 64) and part = tid / nk
+// sums over a wave-uniform share of the other tiles (the part-th slice
+// o0 <= o < o1 for the right-hand side, the part-th share of every 64-tile
+// block for the W products); the part-0 thread of tile k holds the tile's
+// gain and its conjugate-gradient state; threads with part >= NT / nk (when
+// nk does not divide NT) take no share.  W sits in LDS packed with its zero
+// diagonal, as WT (FP64 while it fits).  The operator of the step uses these
+// W values for its diagonal too, so that i g stays its exact null vector; the
+// right-hand side uses the FP64 tables.  The solve is conjugate gradients
+// preconditioned by that diagonal (Jacobi).
+template <typename WT, int NT>
 __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
-  typedef typename TabPair<TT>::type TT2;
-  constexpr bool tab64 = sizeof(TT) == sizeof(double);
   extern __shared__ __align__(16) unsigned char smem[];
   double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
-  double2 *y = g + kPeelMaxAnt;                   // [kPeelMaxAnt] g_o p_o^* of the current direction
-  float2 *y32 = (float2 *)y;                      // the same, FP32, for the FP32 operator (FP32 tables)
+  double2 *y = g + kPeelMaxAnt;                   // [kPeelMaxAnt] g_o u_o^* of the current direction
   double2 *pa = y + kPeelMaxAnt;                  // [NT] partial sums
   double *pv = (double *)(pa + NT);               // [kPeelMaxAnt] projection scratch
   int *comp = (int *)(pv + kPeelMaxAnt);          // [kPeelMaxAnt] connected component of each tile
@@ -277,8 +276,8 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   const int wb = __builtin_amdgcn_readfirstlane(k >> 6);  // this wave's tiles: 64 wb .. 64 wb + 63
   const int sa = pt < parts ? 64 * pt / parts : 0, sb = pt < parts ? 64 * (pt + 1) / parts : 0;
 
-  const TT2 *X = (const TT2 *)a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
-  const TT *Wf = (const TT *)a.wf + (int64_t)cl * n * n;    // |I|^2 [o n + k], zero for o == k
+  const double2 *X = (const double2 *)a.xt + (int64_t)cl * n * n;  // X[o n + k], zero for o == k
+  const double *Wf = (const double *)a.wf + (int64_t)cl * n * n;    // |I|^2 [o n + k], zero for o == k
   for (int idx = tid; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx - i * n;
     if (i <= j) W[packed_index(n, i, j)] = (WT)Wf[idx];
@@ -291,40 +290,8 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   }
   __syncthreads();
 
-  // sum over this part's o of W_ko v_o (v in LDS), FP32 products and sums:
-  // the step's operator on the mixed path, whose W is FP32 already; the
-  // diagonal term is zero
-  auto wdot32 = [&](const float2 *v) {
-    float2 acc = make_float2(0.f, 0.f);
-    auto add = [&](int p, int o) {
-      const float wv = (float)W[p];
-      const float2 vo = v[o];
-      acc.x = fmaf(wv, vo.x, acc.x);
-      acc.y = fmaf(wv, vo.y, acc.y);
-    };
-    for (int c = 0; 64 * c < n; ++c) {
-      const int oa = min(n, 64 * c + sa), ob = min(n, 64 * c + sb);
-      int L = oa * n - oa * (oa + 1) / 2;
-      if (c < wb) {
-#pragma unroll 4
-        for (int o = oa; o < ob; ++o) {
-          add(L + kr, o);
-          L += n - o - 1;
-        }
-      } else if (c > wb) {
-#pragma unroll 4
-        for (int o = oa; o < ob; ++o) add(U + o, o);
-      } else {
-#pragma unroll 4
-        for (int o = oa; o < ob; ++o) {
-          add(o < kr ? L + kr : U + o, o);
-          L += n - o - 1;
-        }
-      }
-    }
-    return make_double2(acc.x, acc.y);
-  };
-  // the same in FP64 (v FP64), or the sum of W_ko |v_o|^2 (sq)
+  // sum over this part's o of W_ko v_o (v in LDS), or of W_ko |v_o|^2 (sq);
+  // the diagonal term is zero
   auto wdot = [&](const double2 *v, bool sq) {
     double2 acc = make_double2(0.0, 0.0);
     auto add = [&](int p, int o) {
@@ -361,22 +328,21 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
   };
 
   for (int it = 0; it < a.n_iter; ++it) {
-    // r_k = sum_o g_o X_ko - g_k D_k,  D_k = sum_o W_ko |g_o|^2 in FP64
-    // (FP64 tables) or Dt_k, the same sum over the LDS copy of W
+    // r_k = sum_o g_o X_ko - g_k D_k,  D_k = sum_o W_ko |g_o|^2 from the FP64
+    // table; Dt_k, the same sum over the LDS copy of W, is the operator's diagonal
     double2 sx = make_double2(0.0, 0.0);
     double sd = 0.0, sa = 0.0;  // sa: sum of |g_o X_ko|, for the rounding level of r_k
     if (row) {
 #pragma unroll 8
       for (int o = o0; o < o1; ++o) {
         const double2 go = g[o];
-        const TT2 xt = X[(int64_t)o * n + k];
-        const double2 x = make_double2(xt.x, xt.y);
+        const double2 x = X[(int64_t)o * n + k];
         const double g2 = go.x * go.x + go.y * go.y;
         sx.x += go.x * x.x - go.y * x.y;
         sx.y += go.x * x.y + go.y * x.x;
         // |g_o X_ko| sets the rounding level only: an FP32 square root will do
         sa += (double)__builtin_amdgcn_sqrtf((float)(g2 * (x.x * x.x + x.y * x.y)));
-        if constexpr (tab64) sd += g2 * Wf[(int64_t)o * n + k];
+        sd += g2 * Wf[(int64_t)o * n + k];
       }
     }
     const double sdt = wdot(g, true).x;
@@ -403,7 +369,6 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
     __syncthreads();
     if (own) {
       for (int q = 0; q < parts; ++q) Dt += pa[q * nk + k].x;
-      if constexpr (!tab64) D = Dt;
       r.x -= gk.x * D;
       r.y -= gk.y * D;
       scale += sqrt(gk.x * gk.x + gk.y * gk.y) * D;
@@ -429,23 +394,9 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
     double gam_old = 1.0, alpha_old = 1.0;
     int steps = 0;  // workgroup-uniform: every stopping test uses block sums
     for (int cg = 0; cg < a.max_cg; ++cg) {
-      if (own) {
-        const double2 yk = cmul(gk, cconj(u));
-        if constexpr (tab64)
-          y[k] = yk;
-        else
-          y32[k] = make_float2((float)yk.x, (float)yk.y);
-      }
+      if (own) y[k] = cmul(gk, cconj(u));
       __syncthreads();
-      double2 sp;
-      double2 yr;
-      if constexpr (tab64) {
-        sp = wdot(y, false);
-        yr = y[kr];
-      } else {
-        sp = wdot32(y32);
-        yr = make_double2(y32[kr].x, y32[kr].y);
-      }
+      const double2 sp = wdot(y, false), yr = y[kr];
       double dterm = row ? yr.x * sp.x - yr.y * sp.y : 0.0, gterm = 0.0, rterm = 0.0;
       if (own) {
         dterm += Dt * (u.x * u.x + u.y * u.y);
@@ -507,9 +458,10 @@ __global__ __launch_bounds__(NT) void k_gain_solve(GainArgs a) {
 // tile k's gain and conjugate-gradient state.  Same iteration, stopping rules
 // and arithmetic as k_gain_solve's mixed path (FP32 operator, FP64 sums and
 // state), with D_k summed from the same FP32 W.
-template <int NW>
+template <int NW, int RPL>
 __global__ __launch_bounds__(64 * NW) void k_gain_solve_rw(GainArgs a) {
-  constexpr int NT = 64 * NW, RPL = kPeelMaxAnt / 64, OPW = kPeelMaxAnt / NW;
+  // up to 64 RPL tiles: RPL rows per lane, NW column blocks of OPW
+  constexpr int NT = 64 * NW, OPW = 64 * RPL / NW;
   extern __shared__ __align__(16) unsigned char smem[];
   double2 *g = (double2 *)smem;                   // [kPeelMaxAnt] gains
   float2 *y32 = (float2 *)(g + kPeelMaxAnt);      // [kPeelMaxAnt] g_o u_o^* of the current direction
@@ -719,13 +671,13 @@ size_t gain_smem_bytes(int n_ant, bool w64, int threads) {
          3 * (threads / 64) * sizeof(double2) + packed * (w64 ? sizeof(double) : sizeof(float));  // red, redp
 }
 
-template <typename WT, int NT, typename TT>
+template <typename WT, int NT>
 static hipError_t launch_solve(const GainArgs &a, hipStream_t s) {
   const size_t sm = gain_smem_bytes(a.n_ant, sizeof(WT) == sizeof(double), NT);
-  hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<WT, NT, TT>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_gain_solve<WT, NT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gain_solve<WT, NT, TT>), dim3((unsigned)a.ncell), dim3(NT), sm, s, a);
+  hipLaunchKernelGGL((k_gain_solve<WT, NT>), dim3((unsigned)a.ncell), dim3(NT), sm, s, a);
   return hipGetLastError();
 }
 
@@ -750,11 +702,19 @@ hipError_t launch_gain_subtract(const GainArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-constexpr int kRwWaves = 8;  // waves per cell of k_gain_solve_rw
+size_t gain_rw_smem_bytes(int nw) {
+  return kPeelMaxAnt * (sizeof(double2) + sizeof(float2) + nw * sizeof(double2) + sizeof(double) + sizeof(int)) +
+         3 * nw * sizeof(double2);
+}
 
-size_t gain_rw_smem_bytes() {
-  return kPeelMaxAnt * (sizeof(double2) + sizeof(float2) + kRwWaves * sizeof(double2) + sizeof(double) + sizeof(int)) +
-         3 * kRwWaves * sizeof(double2);
+template <int NW, int RPL>
+static hipError_t launch_solve_rw(const GainArgs &a, hipStream_t s) {
+  const size_t sm = gain_rw_smem_bytes(NW);
+  hipError_t e =
+      hipFuncSetAttribute((const void *)k_gain_solve_rw<NW, RPL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gain_solve_rw<NW, RPL>), dim3((unsigned)a.ncell), dim3(64 * NW), sm, s, a);
+  return hipGetLastError();
 }
 
 size_t gain_cell_bytes(int n_ant, bool w32) {
@@ -767,23 +727,11 @@ hipError_t launch_gain(const GainArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
   hipError_t e = a.w32 ? launch_tables<float>(a, s) : launch_tables<double>(a, s);
   if (e != hipSuccess) return e;
-  // FP64 W while it fits; with a.w32 (the mixed path), FP32 tables, FP32 W
-  // and smaller cells, three (256 threads) or two (512 threads) sharing one
-  // CU's LDS, so that their conjugate-gradient steps interleave (the solve
-  // is latency-bound)
-  if (a.w32) {
-    if (3 * gain_smem_bytes(a.n_ant, false, 256) <= kPeelSmemMax) return launch_solve<float, 256, float>(a, s);
-    if (2 * gain_smem_bytes(a.n_ant, false, 512) <= kPeelSmemMax) return launch_solve<float, 512, float>(a, s);
-    // larger arrays: W in registers (one cell per CU either way, but no LDS
-    // traffic for W and a quarter of the broadcast reads)
-    const size_t sm = gain_rw_smem_bytes();
-    e = hipFuncSetAttribute((const void *)k_gain_solve_rw<kRwWaves>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gain_solve_rw<kRwWaves>, dim3((unsigned)a.ncell), dim3(64 * kRwWaves), sm, s, a);
-    return hipGetLastError();
-  }
-  if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024, double>(a, s);
-  return launch_solve<float, 1024, double>(a, s);
+  // the mixed path (FP32 tables): W in registers, 128 tiles per 4 waves or
+  // 256 per 8 waves; the FP64 path: W in LDS, FP64 while it fits
+  if (a.w32) return a.n_ant <= 128 ? launch_solve_rw<4, 2>(a, s) : launch_solve_rw<8, 4>(a, s);
+  if (gain_smem_bytes(a.n_ant, true, 1024) <= kPeelSmemMax) return launch_solve<double, 1024>(a, s);
+  return launch_solve<float, 1024>(a, s);
 }
 
 }  // namespace vp
