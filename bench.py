@@ -440,6 +440,76 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _host_info():
+    """Host CPU as the oracle runs on it: logical CPUs, model name, OpenMP threads."""
+    import oracle
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "omp_threads": oracle.max_threads()}
+
+
+def cpu_plan(c1_rate, c1_sample):
+    """The oracle's rates on the host beside the GPU figures: one thread (a
+    per-core rate) on the tiny workload and on a fixed subset of the MWA-like
+    rows; all threads on the tiny workload, on the MWA-like sample (timed in
+    the main leg), on every visibility of the Fornax-like workload, on a
+    deterministic subset of the large peel's rows (extrapolated to the whole
+    observation and labelled so), and on sampled rows of 8 serving requests."""
+    import oracle
+    import synth
+
+    def timed(obs, sky, rows=None, nthreads=0):
+        t0 = time.perf_counter()
+        oracle.predict(obs, sky, rows=rows, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        nrow = len(rows) if rows is not None else obs.n_time * obs.n_bl
+        ev = nrow * obs.n_chan * sky.nominal_components()
+        return {"evals": ev, "s": round(dt, 3), "evals_per_s": ev / dt}
+
+    host = _host_info()
+    out = {"host": host, "one_thread": {}, "all_threads": {}}
+    obs, sky = synth.make_config(0)
+    out["one_thread"]["tiny"] = timed(obs, sky, nthreads=1)
+    out["all_threads"]["tiny"] = timed(obs, sky)
+    obs, sky = synth.make_config(1)
+    rows = np.arange(0, obs.n_time * obs.n_bl, 1777)[:64]
+    r = timed(obs, sky, rows=rows, nthreads=1)
+    r["sample"] = "64 of %d (time, baseline) rows, every 1777th" % (obs.n_time * obs.n_bl)
+    out["one_thread"]["mwa_like_subset"] = r
+    out["all_threads"]["mwa_like_sample"] = {"evals_per_s": c1_rate, "sample": c1_sample}
+    obs, sky = synth.make_config(2)
+    r = timed(obs, sky)
+    r["sample"] = "every visibility (%d)" % obs.n_vis
+    out["all_threads"]["fornax_like_full"] = r
+    obs, sky = synth.make_config(4)
+    nrows = obs.n_time * obs.n_bl
+    rows = np.arange(0, nrows, nrows // 16)[:16]
+    r = timed(obs, sky, rows=rows)
+    r["sample"] = "16 of %d baselines (every %dth), all 384 channels and all components" % (nrows, nrows // 16)
+    r["extrapolated_full_s"] = round(r["s"] * nrows / len(rows), 1)
+    r["extrapolated"] = True
+    out["all_threads"]["large_peel_subset"] = r
+    reqs = synth.make_requests(8)
+    ev, dt = 0, 0.0
+    for q in reqs:
+        nr = q.obs.n_time * q.obs.n_bl
+        rr = np.arange(0, nr, max(1, nr // 16))[:16]
+        x = timed(q.obs, q.sky, rows=rr)
+        ev += x["evals"]
+        dt += x["s"]
+    out["all_threads"]["serving_8_requests"] = {"evals": ev, "s": round(dt, 3), "evals_per_s": ev / dt,
+                                                "sample": "16 rows of each of the first 8 stream requests"}
+    _log("cpu plan: %s" % json.dumps(out))
+    return out
+
+
 def serve_stream(n_requests, rate_hz, budget_bytes):
     """Serving stream: Poisson arrivals of uneven predict / peel-subtract
     requests (tiles 64/128/256, 8-384 channels, 1-14 times, ~2000 points,
@@ -493,6 +563,8 @@ def serve_stream(n_requests, rate_hz, budget_bytes):
                 evals += r.obs.n_vis * r.sky.nominal_components()
         time.sleep(0.0002)
     wall = (max(done_t) - start) / 1e9
+    time.sleep(0.05)  # the persistent kernel's idle exit, so that its last launch is counted
+    launches, resident_ms = vp.vp_serve_stats(ctx)
     # the same requests back to back through vp_predict / vp_subtract, for the
     # serving efficiency
     stream = torch.cuda.current_stream()
@@ -512,9 +584,12 @@ def serve_stream(n_requests, rate_hz, budget_bytes):
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "max_ms": float(lat.max()), "wall_s": wall, "requests_per_s": len(reqs) / wall,
            "evals_per_s": evals / wall, "precision": "mixed", "output": "complex64",
-           "back_to_back_evals_per_s": evals / standalone, "back_to_back_s": standalone}
-    _log("serving: p50 %.1f ms, p99 %.1f ms, %.2e evals/s over %.1f s"
-         % (out["p50_ms"], out["p99_ms"], out["evals_per_s"], wall))
+           "back_to_back_evals_per_s": evals / standalone, "back_to_back_s": standalone,
+           "kernel_launches": launches, "kernel_resident_s": resident_ms / 1e3,
+           "resident_over_back_to_back": resident_ms / 1e3 / standalone}
+    _log("serving: p50 %.1f ms, p99 %.1f ms, %.2e evals/s over %.1f s; persistent kernel %d launches, "
+         "resident %.2f s against %.2f s back to back" % (out["p50_ms"], out["p99_ms"], out["evals_per_s"], wall,
+                                                       launches, resident_ms / 1e3, standalone))
     return out
 
 
@@ -564,6 +639,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--cpu-rows", type=int, default=12288)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu-plan", action="store_true", help="only the MWA-like oracle sample")
+    ap.add_argument("--only-cpu-plan", action="store_true", help="run the oracle's host-rate plan alone")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
@@ -596,6 +673,9 @@ def main():
         return
     if args.only_peel:
         print(json.dumps(calibrated_peel()), flush=True)
+        return
+    if args.only_cpu_plan:
+        print(json.dumps(cpu_plan(None, None)), flush=True)
         return
     if args.only_paper_peel:
         print(json.dumps(paper_peel()), flush=True)
@@ -695,6 +775,9 @@ def main():
                "sample": "%d of %d (time, baseline) rows x all %d channels x all components; %.1f s"
                          % (len(rows), nrows, K, dt)}
         _log("oracle: %.3e evals/s on %d threads; sampled error / total flux = %.3e" % (cpu["value"], threads, err))
+        cpu["gpu_over_oracle"] = value / cpu["value"]
+        if not args.no_cpu_plan:
+            cpu["plan"] = cpu_plan(cpu["value"], cpu["sample"])
 
     vp.vp_destroy_sky(sh)
     vp.vp_destroy_obs(oh)

@@ -241,6 +241,13 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket);
  * poll.  Thread-safe. */
 int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res);
 
+/* Serving measurement: the number of completed launches of the persistent
+ * serving kernel since the context's first vp_submit and their total
+ * duration in ms (HIP events around each launch on the kernel's stream; a
+ * launch still running is not counted).  Zeros before the first vp_submit.
+ * Errors: VP_EINVAL. */
+int vp_serve_stats(vp_ctx *ctx, uint64_t *launches, double *resident_ms);
+
 /* HBM footprint (bytes) that admission charges for `job`.  Errors: VP_EINVAL. */
 int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes);
 

@@ -75,8 +75,10 @@ struct Scheduler {
   std::vector<uint64_t> slot_target, slot_ttarget;
   uint64_t tail = 0, ring_inflight = 0;
   hipStream_t kstream = nullptr, aux = nullptr;
-  hipEvent_t kev = nullptr;
+  hipEvent_t kev0 = nullptr, kev = nullptr;  // around each launch of the persistent kernel
   bool launched = false;
+  uint64_t launches = 0;   // completed launches
+  double resident_ms = 0;  // their total duration
   uint64_t epoch = 0;  // launch counter; workers of a launch exit together
   int grid = 0;
   uint64_t idle_ticks = 0;
@@ -203,19 +205,31 @@ static int admit(Scheduler *s, JobRec *j) {
   return VP_OK;
 }
 
+// A finished launch of the persistent kernel is counted (launches, resident
+// time) and forgotten; hipErrorNotReady while it runs, its error if it failed.
+static hipError_t reap_kernel(Scheduler *s) {
+  if (!s->launched) return hipSuccess;
+  hipError_t q = hipEventQuery(s->kev);
+  if (q == hipErrorNotReady) return q;
+  s->launched = false;
+  if (q != hipSuccess) return q;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, s->kev0, s->kev) == hipSuccess) s->resident_ms += ms;
+  s->launches += 1;
+  return hipSuccess;
+}
+
 static int ensure_kernel(Scheduler *s) {
-  if (s->launched) {
-    hipError_t q = hipEventQuery(s->kev);
-    if (q == hipErrorNotReady) return VP_OK;
-    s->launched = false;
-    if (q != hipSuccess) return hip_error(q, "serving kernel");
-  }
+  const hipError_t q = reap_kernel(s);
+  if (q == hipErrorNotReady) return VP_OK;
+  if (q != hipSuccess) return hip_error(q, "serving kernel");
   uint64_t head = 0;
   hipError_t e = hipMemcpyAsync(&head, &s->D->head, sizeof(head), hipMemcpyDeviceToHost, s->aux);
   if (e == hipSuccess) e = hipStreamSynchronize(s->aux);
   if (e != hipSuccess) return hip_error(e, "reading the serving queue head");
   if (head >= s->tail) return VP_OK;
-  e = launch_serve(s->H_dev, s->D, s->idle_ticks, ++s->epoch, s->grid, s->kstream);
+  e = hipEventRecord(s->kev0, s->kstream);
+  if (e == hipSuccess) e = launch_serve(s->H_dev, s->D, s->idle_ticks, ++s->epoch, s->grid, s->kstream);
   if (e == hipSuccess) e = hipEventRecord(s->kev, s->kstream);
   if (e != hipSuccess) return hip_error(e, "launching the serving kernel");
   s->launched = true;
@@ -322,6 +336,8 @@ static void scheduler_loop(Scheduler *s) {
     if (!s->running.empty()) {
       int rc = ensure_kernel(s);
       if (rc != VP_OK) abandon_running(s, rc);
+    } else if (s->launched && hipEventQuery(s->kev) == hipSuccess) {
+      (void)reap_kernel(s);  // idle: count the launch that just exited
     }
     if (s->quit && s->queue.empty() && s->running.empty()) break;
     if (s->queue.empty() && s->running.empty())
@@ -347,7 +363,8 @@ static int start_scheduler(vp_ctx *ctx, Scheduler **out) {
   if (e == hipSuccess) e = hipMemset(s->D, 0, sizeof(ServeDev));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->kev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&s->kev0);
+  if (e == hipSuccess) e = hipEventCreate(&s->kev);
   if (e == hipSuccess) e = serve_grid(&s->grid);
   int rate_khz = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device);
@@ -355,6 +372,7 @@ static int start_scheduler(vp_ctx *ctx, Scheduler **out) {
   if (e != hipSuccess) {
     int rc = hip_error(e, "starting the serving scheduler");
     if (s->kev) (void)hipEventDestroy(s->kev);
+    if (s->kev0) (void)hipEventDestroy(s->kev0);
     if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->kstream) (void)hipStreamDestroy(s->kstream);
     if (s->D) (void)hipFree(s->D);
@@ -396,6 +414,7 @@ void serve_shutdown(vp_ctx *ctx) {
   (void)hipStreamSynchronize(s->aux);
   for (auto &kv : s->jobs) delete kv.second;
   (void)hipEventDestroy(s->kev);
+  (void)hipEventDestroy(s->kev0);
   (void)hipStreamDestroy(s->aux);
   (void)hipStreamDestroy(s->kstream);
   (void)hipFree(s->D);
@@ -459,6 +478,20 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
     *ticket = j->ticket;
   }
   s->cv.notify_all();
+  return VP_OK;
+}
+
+int vp_serve_stats(vp_ctx *ctx, uint64_t *launches, double *resident_ms) {
+  if (!ctx || !launches || !resident_ms) return set_error(VP_EINVAL, "NULL argument");
+  Scheduler *s = ctx->sched;
+  if (!s) {
+    *launches = 0;
+    *resident_ms = 0.0;
+    return VP_OK;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  *launches = s->launches;
+  *resident_ms = s->resident_ms;
   return VP_OK;
 }
 

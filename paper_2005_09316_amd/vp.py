@@ -36,7 +36,7 @@ PRECISIONS = {"fp64": VP_PREC_FP64, "mixed": VP_PREC_MIXED, "mixed_bf16": VP_PRE
 
 # every symbol declared in include/vp.h
 EXPORTS = ["vp_create_ctx", "vp_destroy_ctx", "vp_create_obs", "vp_destroy_obs", "vp_create_sky",
-           "vp_destroy_sky", "vp_predict", "vp_predict_noalloc", "vp_subtract", "vp_peel", "vp_submit", "vp_poll", "vp_job_footprint",
+           "vp_destroy_sky", "vp_predict", "vp_predict_noalloc", "vp_subtract", "vp_peel", "vp_submit", "vp_poll", "vp_serve_stats", "vp_job_footprint",
            "vp_profile", "vp_profile_read", "vp_last_error", "vp_version"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "vp_submit": ([vp, ctypes.POINTER(vp_job), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "vp_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(vp_job_result)], ctypes.c_int),
         "vp_job_footprint": ([vp, ctypes.POINTER(vp_job), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "vp_serve_stats": ([vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "vp_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "vp_profile_read": ([vp, _i64p, _dp], ctypes.c_int),
         "vp_last_error": ([], ctypes.c_char_p),
@@ -232,6 +233,13 @@ def vp_submit(ctx: int, kind: int, sky: int, obs: int, precision: int, dtype: in
     t = ctypes.c_uint64()
     _check(load().vp_submit(ctx, ctypes.byref(j), ctypes.byref(t)))
     return t.value
+
+
+def vp_serve_stats(ctx: int):
+    """(launches, resident_ms) of the persistent serving kernel."""
+    n, ms = ctypes.c_uint64(), ctypes.c_double()
+    _check(load().vp_serve_stats(ctx, ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 def vp_poll(ctx: int, ticket: int) -> Optional[dict]:
