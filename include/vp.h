@@ -227,7 +227,12 @@ typedef struct {
 
 /* Enqueue a job; returns a ticket.  The caller's writes to job->vis_dev (the
  * data of a subtract job) must be complete, i.e. the writing stream
- * synchronised, before the call.  Only VP_PREC_MIXED is served.  The job is
+ * synchronised, before the call.  Only VP_PREC_MIXED is served: the
+ * persistent kernel that runs every admitted job's tiles is one compiled
+ * instance of the mixed path, and its register use sets the occupancy that
+ * all jobs share (an FP64 instance beside it would run at lower occupancy and
+ * serialise against it); FP64 work goes through vp_predict / vp_subtract on a
+ * caller stream, which may run beside serving.  The job is
  * admitted when its HBM footprint
  * fits the budget minus what admitted jobs hold, in FIFO order; admitted jobs
  * are expanded into tiles that a persistent device kernel processes together

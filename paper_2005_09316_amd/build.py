@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvp.so")
-SOURCES = ["vp_kernels.hip", "vp_calib.hip", "vp_api.cpp", "vp_serve.cpp", "vp_peel.cpp"]
+SOURCES = ["vp_kernels.hip", "vp_calib.hip", "vp_api.cpp", "vp_serve.cpp", "serve_core.cpp", "vp_peel.cpp"]
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

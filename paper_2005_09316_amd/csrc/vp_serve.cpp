@@ -1,88 +1,29 @@
 // vp_serve.cpp -- continuous batching: vp_submit / vp_poll.
 //
-// A scheduler thread per context admits queued jobs in FIFO order when their
-// HBM footprint fits the budget minus what admitted jobs hold (and a job slot
-// and ring space are free).  Admission writes the job's arguments into a
-// host-mapped slot and appends its items to a host-mapped ring: first table
-// items when the job's (sky, observation) pair has no tables yet, then -- once
-// the host sees the tables built -- its visibility tiles.  A persistent kernel
-// (k_serve) on its own stream claims items from the ring as they appear, so
-// jobs that arrive while others run share the device tile by tile.  The
-// kernel exits after a short idle period; the scheduler relaunches it when
-// items are waiting.  Completion is signalled per job through host-mapped
-// flags.
+// The scheduling policy (FIFO admission by HBM footprint, tickets, the
+// scheduler thread) is ServeCore (serve_core.cpp); this file is its device
+// side.  Admission writes the job's arguments into a host-mapped slot and
+// appends its items to a host-mapped ring: first table items when the job's
+// (sky, observation) pair has no tables yet, then -- once the host sees the
+// tables built -- its visibility tiles.  A persistent kernel (k_serve) on its
+// own stream claims items from the ring as they appear, so jobs that arrive
+// while others run share the device tile by tile.  The kernel exits after a
+// short idle period; the scheduler relaunches it when items are waiting.
+// Completion is signalled per job through host-mapped flags.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
 #include <atomic>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <mutex>
-#include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/vp.h"
+#include "serve_core.h"
 #include "vp_internal.h"
 #include "vp_objects.h"
 
 namespace vp {
-
-static uint64_t now_ns() {
-  timespec ts;
-  clock_gettime(CLOCK_MONOTONIC, &ts);
-  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
-}
-
-enum JobState { kQueued = 0, kRunning = 1, kDone = 2 };
-
-struct JobRec {
-  uint64_t ticket = 0;
-  vp_job job{};
-  int state = kQueued;
-  int status = VP_OK;
-  uint64_t t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
-  uint64_t dev_start = 0, dev_done = 0;  // device wall clock at its first tile's start, last tile's end
-  uint64_t footprint = 0;
-  int slot = -1;
-  uint64_t seq = 0, seq_table = 0;
-  int64_t ntiles = 0, ntable = 0;
-  DerivedEntry *d = nullptr;
-  bool owner = false;     // this job builds the pair's tables
-  bool tiles_out = false; // tiles published
-};
-
-struct Scheduler {
-  vp_ctx *ctx = nullptr;
-  std::mutex mu;
-  std::condition_variable cv;
-  std::thread th;
-  bool quit = false;
-  std::string init_error;
-  int init_rc = VP_OK;
-  bool init_done = false;
-  std::deque<JobRec *> queue;
-  std::vector<JobRec *> running;
-  std::unordered_map<uint64_t, JobRec *> jobs;
-  uint64_t next_ticket = 1, next_seq = 1;
-  uint64_t in_use = 0;
-  ServeHost *H = nullptr;      // host pointer
-  ServeHost *H_dev = nullptr;  // the same memory as seen by the device
-  ServeDev *D = nullptr;
-  std::vector<int> free_slots;
-  std::vector<uint64_t> slot_target, slot_ttarget;
-  uint64_t tail = 0, ring_inflight = 0;
-  hipStream_t kstream = nullptr, aux = nullptr;
-  hipEvent_t kev0 = nullptr, kev = nullptr;  // around each launch of the persistent kernel
-  bool launched = false;
-  uint64_t launches = 0;   // completed launches
-  double resident_ms = 0;  // their total duration
-  uint64_t epoch = 0;  // launch counter; workers of a launch exit together
-  int grid = 0;
-  uint64_t idle_ticks = 0;
-};
 
 uint64_t job_footprint(const vp_sky *sky, const vp_obs *obs, int dtype) {
   const uint64_t nvis = (uint64_t)obs->T * obs->B * obs->K;
@@ -104,45 +45,102 @@ static int check_job(vp_ctx *ctx, const vp_job *job) {
   return VP_OK;
 }
 
-// --- scheduler thread -------------------------------------------------------
-
-static void finish(Scheduler *s, JobRec *j, int status) {
-  j->status = status;
-  j->state = kDone;
-  j->t_done = now_ns();
-  if (j->t_start == 0) j->t_start = j->t_done;
-  std::lock_guard<std::mutex> lk(s->ctx->mu);
-  const_cast<vp_sky *>(j->job.sky)->jobs -= 1;
-  const_cast<vp_obs *>(j->job.obs)->jobs -= 1;
+static int64_t table_items(const vp_sky *sky, const vp_obs *obs) {
+  const int64_t J = (int64_t)sky->P + sky->G + sky->S;
+  return (J + kTileRows - 1) / kTileRows + (J * obs->Kpad + kTileRows - 1) / kTileRows;
 }
 
-static void publish(Scheduler *s, int slot, int64_t n, bool table) {
+// What the device side keeps per job.
+struct JobExt {
+  vp_job job{};
+  int slot = -1;
+  uint64_t seq = 0, seq_table = 0;
+  int64_t ntiles = 0, ntable = 0;
+  DerivedEntry *d = nullptr;
+  bool owner = false;      // this job builds the pair's tables
+  bool tiles_out = false;  // tiles published
+};
+
+static JobExt &ext(CoreJob &j) { return *(JobExt *)j.payload; }
+
+class HipExecutor : public ServeExecutor {
+ public:
+  vp_ctx *ctx = nullptr;
+  ServeHost *H = nullptr;      // host pointer
+  ServeHost *H_dev = nullptr;  // the same memory as seen by the device
+  ServeDev *D = nullptr;
+  std::vector<int> free_slots;
+  std::vector<uint64_t> slot_target, slot_ttarget;
+  uint64_t tail = 0, ring_inflight = 0, next_seq = 1;
+  hipStream_t kstream = nullptr, aux = nullptr;
+  hipEvent_t kev0 = nullptr, kev = nullptr;  // around each launch of the persistent kernel
+  bool launched = false;
+  uint64_t epoch = 0;  // launch counter; workers of a launch exit together
+  int grid = 0;
+  uint64_t idle_ticks = 0;
+  std::mutex stats_mu;     // launches and resident_ms, read by vp_serve_stats
+  uint64_t launches = 0;   // completed launches
+  double resident_ms = 0;  // their total duration
+
+  int init(vp_ctx *c);
+  void teardown();
+
+  void thread_start() override { (void)hipSetDevice(ctx->device); }
+  bool has_room(const CoreJob &j) override;
+  uint64_t evictable_bytes() override { return serve_evictable_bytes(ctx); }
+  void evict() override { serve_evict(ctx); }
+  int admit(CoreJob &j) override;
+  bool poll(CoreJob &j) override;
+  int kick() override;
+  void idle() override;
+  void abandon(const std::vector<CoreJob *> &running, int rc) override;
+  void finished(CoreJob &j) override;
+  void retired(CoreJob &j) override;
+
+ private:
+  void publish(int slot, int64_t n, bool table);
+  void publish_tiles(JobExt &x);
+  hipError_t reap_kernel();
+};
+
+struct Scheduler {
+  HipExecutor ex;
+  ServeCore *core = nullptr;
+};
+
+bool HipExecutor::has_room(const CoreJob &j) {
+  const JobExt &x = *(const JobExt *)j.payload;
+  return !free_slots.empty() &&
+         ring_inflight + (uint64_t)x.ntiles + (uint64_t)table_items(x.job.sky, x.job.obs) <= kRingSize;
+}
+
+void HipExecutor::publish(int slot, int64_t n, bool table) {
   const uint64_t flag = table ? (1ull << 47) : 0ull;
   for (int64_t t = 0; t < n; ++t)
-    s->H->ring[(s->tail + (uint64_t)t) & (kRingSize - 1)] = ((uint64_t)slot << 48) | flag | (uint64_t)t;
-  s->tail += (uint64_t)n;
+    H->ring[(tail + (uint64_t)t) & (kRingSize - 1)] = ((uint64_t)slot << 48) | flag | (uint64_t)t;
+  tail += (uint64_t)n;
   std::atomic_thread_fence(std::memory_order_release);
-  __atomic_store_n(&s->H->tail, s->tail, __ATOMIC_RELEASE);
+  __atomic_store_n(&H->tail, tail, __ATOMIC_RELEASE);
 }
 
 // Tile phase: the job's tables are ready; publish its tiles under a fresh
 // sequence number (workers acquire once per newer sequence number, which
 // makes the freshly built tables visible to them).
-static void publish_tiles(Scheduler *s, JobRec *j) {
-  ServeJobDesc &desc = s->H->jobs[j->slot];
-  j->seq = s->next_seq++;
-  s->slot_target[j->slot] += (uint64_t)j->ntiles;
-  desc.seq = j->seq;
-  desc.done_target = s->slot_target[j->slot];
+void HipExecutor::publish_tiles(JobExt &x) {
+  ServeJobDesc &desc = H->jobs[x.slot];
+  x.seq = next_seq++;
+  slot_target[x.slot] += (uint64_t)x.ntiles;
+  desc.seq = x.seq;
+  desc.done_target = slot_target[x.slot];
   std::atomic_thread_fence(std::memory_order_release);
-  publish(s, j->slot, j->ntiles, false);
-  j->tiles_out = true;
+  publish(x.slot, x.ntiles, false);
+  x.tiles_out = true;
 }
 
-static int admit(Scheduler *s, JobRec *j) {
-  vp_ctx *ctx = s->ctx;
-  const vp_sky *sky = j->job.sky;
-  const vp_obs *obs = j->job.obs;
+int HipExecutor::admit(CoreJob &j) {
+  JobExt &x = ext(j);
+  const vp_sky *sky = x.job.sky;
+  const vp_obs *obs = x.job.obs;
   DerivedEntry *d = nullptr;
   bool build = false;
   int rc = serve_derived(ctx, sky, obs, &d, &build);
@@ -159,27 +157,24 @@ static int admit(Scheduler *s, JobRec *j) {
   a.S = sky->S;
   a.d = d->d;
   a.t = sky->tiles;
-  a.vis = j->job.vis_dev;
-  a.subtract = j->job.kind == VP_JOB_SUBTRACT;
-  a.c64 = j->job.dtype == VP_C64;
+  a.vis = x.job.vis_dev;
+  a.subtract = x.job.kind == VP_JOB_SUBTRACT;
+  a.c64 = x.job.dtype == VP_C64;
   a.conj = obs->sign < 0;
   a.n_rb = (int)((a.nrows + kTileRows - 1) / kTileRows);
   a.n_cb = obs->Kpad / kPgChan;
   a.dfk = obs->dfk;
   a.uniform = obs->uniform;
   a.fresh = 0;
-  const int slot = s->free_slots.back();
-  s->free_slots.pop_back();
-  j->slot = slot;
-  j->d = d;
-  ServeJobDesc &desc = s->H->jobs[slot];
+  const int slot = free_slots.back();
+  free_slots.pop_back();
+  x.slot = slot;
+  x.d = d;
+  ServeJobDesc &desc = H->jobs[slot];
   desc.a = a;
-  desc.ntiles = j->ntiles;
+  desc.ntiles = x.ntiles;
   desc.ntable = 0;
-  s->ring_inflight += (uint64_t)j->ntiles;
-  s->in_use += j->footprint;
-  j->t_admit = now_ns();
-  j->state = kRunning;
+  ring_inflight += (uint64_t)x.ntiles;
   const int J = sky->P + sky->G + sky->S;
   if (build && J == 0) {
     derived_built(ctx, d);
@@ -187,53 +182,104 @@ static int admit(Scheduler *s, JobRec *j) {
   }
   if (build) {
     // table phase: the persistent kernel builds the pair's tables
-    j->owner = true;
-    j->ntable = (int64_t)(J + kTileRows - 1) / kTileRows + ((int64_t)J * obs->Kpad + kTileRows - 1) / kTileRows;
-    j->seq_table = s->next_seq++;
-    s->slot_ttarget[slot] += (uint64_t)j->ntable;
+    x.owner = true;
+    x.ntable = table_items(sky, obs);
+    x.seq_table = next_seq++;
+    slot_ttarget[slot] += (uint64_t)x.ntable;
     desc.da = make_derive_args(sky, obs, d->d);
     desc.fa = make_flux_args(sky, obs, d->d);
-    desc.ntable = j->ntable;
-    desc.seq_table = j->seq_table;
-    desc.table_target = s->slot_ttarget[slot];
-    s->ring_inflight += (uint64_t)j->ntable;
+    desc.ntable = x.ntable;
+    desc.seq_table = x.seq_table;
+    desc.table_target = slot_ttarget[slot];
+    ring_inflight += (uint64_t)x.ntable;
     std::atomic_thread_fence(std::memory_order_release);
-    publish(s, slot, j->ntable, true);
+    publish(slot, x.ntable, true);
   } else if (derived_ready(ctx, d)) {
-    publish_tiles(s, j);
+    publish_tiles(x);
   }
   return VP_OK;
 }
 
+bool HipExecutor::poll(CoreJob &j) {
+  JobExt &x = ext(j);
+  if (!x.tiles_out) {
+    if (x.owner && __atomic_load_n(&H->tabled[x.slot], __ATOMIC_ACQUIRE) == x.seq_table) {
+      derived_built(ctx, x.d);
+      x.owner = false;
+    }
+    if (!x.owner && derived_ready(ctx, x.d)) publish_tiles(x);
+    return false;
+  }
+  const uint64_t st = __atomic_load_n(&H->started[x.slot], __ATOMIC_ACQUIRE);
+  if (j.t_start == 0 && st == x.seq) {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    j.t_start = (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+    j.dev_start = __atomic_load_n(&H->started_clk[x.slot], __ATOMIC_RELAXED);
+  }
+  const uint64_t fin = __atomic_load_n(&H->finished[x.slot], __ATOMIC_ACQUIRE);
+  if (fin != x.seq) return false;
+  if (j.dev_start == 0) j.dev_start = __atomic_load_n(&H->started_clk[x.slot], __ATOMIC_RELAXED);
+  j.dev_done = __atomic_load_n(&H->finished_clk[x.slot], __ATOMIC_RELAXED);
+  j.status = VP_OK;
+  return true;
+}
+
+void HipExecutor::finished(CoreJob &j) {
+  JobExt &x = ext(j);
+  ring_inflight -= (uint64_t)(x.ntiles + x.ntable);
+  free_slots.push_back(x.slot);
+  serve_release_derived(ctx, x.d);
+}
+
+void HipExecutor::retired(CoreJob &j) {
+  JobExt *x = (JobExt *)j.payload;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const_cast<vp_sky *>(x->job.sky)->jobs -= 1;
+    const_cast<vp_obs *>(x->job.obs)->jobs -= 1;
+  }
+  delete x;
+  j.payload = nullptr;
+}
+
 // A finished launch of the persistent kernel is counted (launches, resident
 // time) and forgotten; hipErrorNotReady while it runs, its error if it failed.
-static hipError_t reap_kernel(Scheduler *s) {
-  if (!s->launched) return hipSuccess;
-  hipError_t q = hipEventQuery(s->kev);
+hipError_t HipExecutor::reap_kernel() {
+  if (!launched) return hipSuccess;
+  hipError_t q = hipEventQuery(kev);
   if (q == hipErrorNotReady) return q;
-  s->launched = false;
+  launched = false;
   if (q != hipSuccess) return q;
   float ms = 0.f;
-  if (hipEventElapsedTime(&ms, s->kev0, s->kev) == hipSuccess) s->resident_ms += ms;
-  s->launches += 1;
+  if (hipEventElapsedTime(&ms, kev0, kev) != hipSuccess) ms = 0.f;
+  std::lock_guard<std::mutex> lk(stats_mu);
+  resident_ms += ms;
+  launches += 1;
   return hipSuccess;
 }
 
-static int ensure_kernel(Scheduler *s) {
-  const hipError_t q = reap_kernel(s);
+int HipExecutor::kick() {
+  const hipError_t q = reap_kernel();
   if (q == hipErrorNotReady) return VP_OK;
   if (q != hipSuccess) return hip_error(q, "serving kernel");
   uint64_t head = 0;
-  hipError_t e = hipMemcpyAsync(&head, &s->D->head, sizeof(head), hipMemcpyDeviceToHost, s->aux);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->aux);
+  hipError_t e = hipMemcpyAsync(&head, &D->head, sizeof(head), hipMemcpyDeviceToHost, aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(aux);
   if (e != hipSuccess) return hip_error(e, "reading the serving queue head");
-  if (head >= s->tail) return VP_OK;
-  e = hipEventRecord(s->kev0, s->kstream);
-  if (e == hipSuccess) e = launch_serve(s->H_dev, s->D, s->idle_ticks, ++s->epoch, s->grid, s->kstream);
-  if (e == hipSuccess) e = hipEventRecord(s->kev, s->kstream);
+  if (head >= tail) return VP_OK;
+  e = hipEventRecord(kev0, kstream);
+  if (e == hipSuccess) e = launch_serve(H_dev, D, idle_ticks, ++epoch, grid, kstream);
+  if (e == hipSuccess) e = hipEventRecord(kev, kstream);
   if (e != hipSuccess) return hip_error(e, "launching the serving kernel");
-  s->launched = true;
+  launched = true;
   return VP_OK;
+}
+
+void HipExecutor::idle() {
+  // count a launch that exited while nothing ran; an error stays with the
+  // event and surfaces at the next kick()
+  if (launched && hipEventQuery(kev) == hipSuccess) (void)reap_kernel();
 }
 
 // The persistent kernel could not be launched, or its launch failed on the
@@ -244,181 +290,98 @@ static int ensure_kernel(Scheduler *s) {
 // marked ready; each slot's completion targets are re-read from the device
 // counters, which count only the items that ran, before the slot is reused
 // (a slot whose counters cannot be read stays out of use).
-static void abandon_running(Scheduler *s, int rc) {
+void HipExecutor::abandon(const std::vector<CoreJob *> &running, int rc) {
+  (void)rc;
   bool synced = false;
   std::vector<uint64_t> done(kServeSlots), tdone(kServeSlots);
   {
-    const uint64_t tail = s->tail;
-    hipError_t e = hipMemcpyAsync(&s->D->head, &tail, sizeof(tail), hipMemcpyHostToDevice, s->aux);
-    if (e == hipSuccess) e = hipMemcpyAsync(done.data(), s->D->done, sizeof(uint64_t) * kServeSlots,
-                                            hipMemcpyDeviceToHost, s->aux);
-    if (e == hipSuccess) e = hipMemcpyAsync(tdone.data(), s->D->tdone, sizeof(uint64_t) * kServeSlots,
-                                            hipMemcpyDeviceToHost, s->aux);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->aux);
+    const uint64_t t = tail;
+    hipError_t e = hipMemcpyAsync(&D->head, &t, sizeof(t), hipMemcpyHostToDevice, aux);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(done.data(), D->done, sizeof(uint64_t) * kServeSlots, hipMemcpyDeviceToHost, aux);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tdone.data(), D->tdone, sizeof(uint64_t) * kServeSlots, hipMemcpyDeviceToHost, aux);
+    if (e == hipSuccess) e = hipStreamSynchronize(aux);
     synced = e == hipSuccess;
   }
   // jobs waiting for tables that an abandoned owner was to build let go of
   // them before the owner drops them
-  for (JobRec *j : s->running)
-    if (!j->owner) serve_release_derived(s->ctx, j->d);
-  for (JobRec *j : s->running)
-    if (j->owner) serve_abandon_derived(s->ctx, j->d);
-  for (JobRec *j : s->running) {
-    s->in_use -= j->footprint;
-    s->ring_inflight -= (uint64_t)(j->ntiles + j->ntable);
+  for (CoreJob *j : running)
+    if (!ext(*j).owner) serve_release_derived(ctx, ext(*j).d);
+  for (CoreJob *j : running)
+    if (ext(*j).owner) serve_abandon_derived(ctx, ext(*j).d);
+  for (CoreJob *j : running) {
+    JobExt &x = ext(*j);
+    ring_inflight -= (uint64_t)(x.ntiles + x.ntable);
     if (synced) {
-      s->slot_target[j->slot] = done[j->slot];
-      s->slot_ttarget[j->slot] = tdone[j->slot];
-      s->free_slots.push_back(j->slot);
-    }
-    finish(s, j, rc);
-  }
-  s->running.clear();
-}
-
-static void scheduler_loop(Scheduler *s) {
-  (void)hipSetDevice(s->ctx->device);
-  std::unique_lock<std::mutex> lk(s->mu);
-  while (true) {
-    // completions
-    for (size_t i = 0; i < s->running.size();) {
-      JobRec *j = s->running[i];
-      if (!j->tiles_out) {
-        if (j->owner && __atomic_load_n(&s->H->tabled[j->slot], __ATOMIC_ACQUIRE) == j->seq_table) {
-          derived_built(s->ctx, j->d);
-          j->owner = false;
-        }
-        if (!j->owner && derived_ready(s->ctx, j->d)) publish_tiles(s, j);
-        ++i;
-        continue;
-      }
-      const uint64_t st = __atomic_load_n(&s->H->started[j->slot], __ATOMIC_ACQUIRE);
-      if (j->t_start == 0 && st == j->seq) {
-        j->t_start = now_ns();
-        j->dev_start = __atomic_load_n(&s->H->started_clk[j->slot], __ATOMIC_RELAXED);
-      }
-      const uint64_t fin = __atomic_load_n(&s->H->finished[j->slot], __ATOMIC_ACQUIRE);
-      if (fin == j->seq) {
-        if (j->dev_start == 0) j->dev_start = __atomic_load_n(&s->H->started_clk[j->slot], __ATOMIC_RELAXED);
-        j->dev_done = __atomic_load_n(&s->H->finished_clk[j->slot], __ATOMIC_RELAXED);
-        s->in_use -= j->footprint;
-        s->ring_inflight -= (uint64_t)(j->ntiles + j->ntable);
-        s->free_slots.push_back(j->slot);
-        serve_release_derived(s->ctx, j->d);
-        finish(s, j, VP_OK);
-        s->running[i] = s->running.back();
-        s->running.pop_back();
-      } else {
-        ++i;
-      }
-    }
-    // admissions, FIFO
-    while (!s->queue.empty()) {
-      JobRec *j = s->queue.front();
-      const uint64_t J = (uint64_t)j->job.sky->P + j->job.sky->G + j->job.sky->S;
-      const uint64_t table_items = (J + kTileRows - 1) / kTileRows + (J * j->job.obs->Kpad + kTileRows - 1) / kTileRows;
-      if (s->free_slots.empty() || s->ring_inflight + (uint64_t)j->ntiles + table_items > kRingSize) break;
-      // the budget covers admitted jobs and the tables that finished serving
-      // jobs built and nothing else uses; those are released when they stand
-      // in the way of the next job
-      if (s->in_use + j->footprint > s->ctx->budget) break;
-      if (s->in_use + serve_evictable_bytes(s->ctx) + j->footprint > s->ctx->budget) {
-        serve_evict(s->ctx);
-        if (s->in_use + serve_evictable_bytes(s->ctx) + j->footprint > s->ctx->budget) break;
-      }
-      s->queue.pop_front();
-      int rc = admit(s, j);
-      if (rc != VP_OK)
-        finish(s, j, rc);
-      else
-        s->running.push_back(j);
-    }
-    if (!s->running.empty()) {
-      int rc = ensure_kernel(s);
-      if (rc != VP_OK) abandon_running(s, rc);
-    } else if (s->launched && hipEventQuery(s->kev) == hipSuccess) {
-      (void)reap_kernel(s);  // idle: count the launch that just exited
-    }
-    if (s->quit && s->queue.empty() && s->running.empty()) break;
-    if (s->queue.empty() && s->running.empty())
-      s->cv.wait_for(lk, std::chrono::milliseconds(2));
-    else {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-      lk.lock();
+      slot_target[x.slot] = done[x.slot];
+      slot_ttarget[x.slot] = tdone[x.slot];
+      free_slots.push_back(x.slot);
     }
   }
 }
 
-static int start_scheduler(vp_ctx *ctx, Scheduler **out) {
-  Scheduler *s = new Scheduler();
-  s->ctx = ctx;
+int HipExecutor::init(vp_ctx *c) {
+  ctx = c;
   DeviceGuard g(ctx->device);
-  hipError_t e = hipHostMalloc((void **)&s->H, sizeof(ServeHost), hipHostMallocMapped | hipHostMallocCoherent);
+  hipError_t e = hipHostMalloc((void **)&H, sizeof(ServeHost), hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) {
-    std::memset(s->H, 0, sizeof(ServeHost));
-    e = hipHostGetDevicePointer((void **)&s->H_dev, s->H, 0);
+    std::memset(H, 0, sizeof(ServeHost));
+    e = hipHostGetDevicePointer((void **)&H_dev, H, 0);
   }
-  if (e == hipSuccess) e = hipMalloc((void **)&s->D, sizeof(ServeDev));
-  if (e == hipSuccess) e = hipMemset(s->D, 0, sizeof(ServeDev));
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreate(&s->kev0);
-  if (e == hipSuccess) e = hipEventCreate(&s->kev);
-  if (e == hipSuccess) e = serve_grid(&s->grid);
+  if (e == hipSuccess) e = hipMalloc((void **)&D, sizeof(ServeDev));
+  if (e == hipSuccess) e = hipMemset(D, 0, sizeof(ServeDev));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&kstream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&kev0);
+  if (e == hipSuccess) e = hipEventCreate(&kev);
+  if (e == hipSuccess) e = serve_grid(&grid);
   int rate_khz = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     int rc = hip_error(e, "starting the serving scheduler");
-    if (s->kev) (void)hipEventDestroy(s->kev);
-    if (s->kev0) (void)hipEventDestroy(s->kev0);
-    if (s->aux) (void)hipStreamDestroy(s->aux);
-    if (s->kstream) (void)hipStreamDestroy(s->kstream);
-    if (s->D) (void)hipFree(s->D);
-    if (s->H) (void)hipHostFree(s->H);
-    delete s;
+    teardown();
     return rc;
   }
   // the workgroups exit together after 2 ms without work (the device is then
   // free for other kernels); the scheduler relaunches when items wait
-  s->idle_ticks = (uint64_t)(rate_khz > 0 ? rate_khz : 100000) * 2;
-  s->slot_target.assign(kServeSlots, 0);
-  s->slot_ttarget.assign(kServeSlots, 0);
-  for (int i = kServeSlots - 1; i >= 0; --i) s->free_slots.push_back(i);
-  s->th = std::thread(scheduler_loop, s);
-  *out = s;
+  idle_ticks = (uint64_t)(rate_khz > 0 ? rate_khz : 100000) * 2;
+  slot_target.assign(kServeSlots, 0);
+  slot_ttarget.assign(kServeSlots, 0);
+  for (int i = kServeSlots - 1; i >= 0; --i) free_slots.push_back(i);
   return VP_OK;
+}
+
+void HipExecutor::teardown() {
+  DeviceGuard g(ctx->device);
+  if (H) __atomic_store_n(&H->stop, 1ull, __ATOMIC_RELEASE);
+  if (launched) (void)hipEventSynchronize(kev);
+  if (kstream) (void)hipStreamSynchronize(kstream);
+  if (aux) (void)hipStreamSynchronize(aux);
+  if (kev) (void)hipEventDestroy(kev);
+  if (kev0) (void)hipEventDestroy(kev0);
+  if (aux) (void)hipStreamDestroy(aux);
+  if (kstream) (void)hipStreamDestroy(kstream);
+  if (D) (void)hipFree(D);
+  if (H) (void)hipHostFree(H);
+  kev = kev0 = nullptr;
+  aux = kstream = nullptr;
+  D = nullptr;
+  H = H_dev = nullptr;
+  launched = false;
 }
 
 bool serve_pending(vp_ctx *ctx) {
   Scheduler *s = ctx->sched;
-  if (!s) return false;
-  std::lock_guard<std::mutex> lk(s->mu);
-  return !s->queue.empty() || !s->running.empty();
+  return s && s->core->pending();
 }
 
 void serve_shutdown(vp_ctx *ctx) {
   Scheduler *s = ctx->sched;
   if (!s) return;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->quit = true;
-  }
-  s->cv.notify_all();
-  if (s->th.joinable()) s->th.join();
-  DeviceGuard g(ctx->device);
-  __atomic_store_n(&s->H->stop, 1ull, __ATOMIC_RELEASE);
-  if (s->launched) (void)hipEventSynchronize(s->kev);
-  (void)hipStreamSynchronize(s->kstream);
-  (void)hipStreamSynchronize(s->aux);
-  for (auto &kv : s->jobs) delete kv.second;
-  (void)hipEventDestroy(s->kev);
-  (void)hipEventDestroy(s->kev0);
-  (void)hipStreamDestroy(s->aux);
-  (void)hipStreamDestroy(s->kstream);
-  (void)hipFree(s->D);
-  (void)hipHostFree(s->H);
+  delete s->core;  // drains (nothing is pending here) and stops the thread
+  s->ex.teardown();
   delete s;
   ctx->sched = nullptr;
 }
@@ -447,37 +410,66 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
                      (unsigned long long)ctx->budget);
   const int64_t ntiles = (int64_t)(((int64_t)job->obs->T * job->obs->B + kTileRows - 1) / kTileRows) *
                          (job->obs->Kpad / kPgChan);
-  if ((uint64_t)ntiles > kRingSize || ntiles >= ((int64_t)1 << 48))
+  if ((uint64_t)ntiles + (uint64_t)table_items(job->sky, job->obs) > kRingSize || ntiles >= ((int64_t)1 << 47))
     return set_error(VP_ECAPACITY, "job has %lld tiles, more than the serving ring holds", (long long)ntiles);
+  Scheduler *s = nullptr;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (!ctx->sched) {
-      Scheduler *s = nullptr;
-      rc = start_scheduler(ctx, &s);
-      if (rc != VP_OK) return rc;
-      ctx->sched = s;
+      Scheduler *n = new Scheduler();
+      rc = n->ex.init(ctx);
+      if (rc != VP_OK) {
+        delete n;
+        return rc;
+      }
+      n->core = new ServeCore(&n->ex, ctx->budget);
+      ctx->sched = n;
     }
+    s = ctx->sched;
+    // the job holds its sky and observation from here until it retires
+    const_cast<vp_sky *>(job->sky)->jobs += 1;
+    const_cast<vp_obs *>(job->obs)->jobs += 1;
   }
-  Scheduler *s = ctx->sched;
-  JobRec *j = new JobRec();
-  j->job = *job;
-  j->t_submit = now_ns();
-  if (j->job.t_arrival_ns == 0) j->job.t_arrival_ns = j->t_submit;
+  JobExt *x = new JobExt();
+  x->job = *job;
+  x->ntiles = ntiles;
+  if (x->job.t_arrival_ns == 0) {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    x->job.t_arrival_ns = (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+  }
+  CoreJob *j = new CoreJob();
   j->footprint = fp;
-  j->ntiles = ntiles;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
+  j->payload = x;
+  rc = s->core->submit(j, ticket);
+  if (rc != VP_OK) {  // not reached: the footprint was checked above
     {
-      std::lock_guard<std::mutex> lk2(ctx->mu);
-      const_cast<vp_sky *>(job->sky)->jobs += 1;
-      const_cast<vp_obs *>(job->obs)->jobs += 1;
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      const_cast<vp_sky *>(job->sky)->jobs -= 1;
+      const_cast<vp_obs *>(job->obs)->jobs -= 1;
     }
-    j->ticket = s->next_ticket++;
-    s->jobs[j->ticket] = j;
-    s->queue.push_back(j);
-    *ticket = j->ticket;
+    delete x;
+    delete j;
+    return set_error(rc, "job refused by the scheduler");
   }
-  s->cv.notify_all();
+  return VP_OK;
+}
+
+int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res) {
+  if (!ctx || !res) return set_error(VP_EINVAL, "NULL context or result");
+  Scheduler *s = ctx->sched;
+  if (!s) return set_error(VP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  CoreJob j;
+  const int rc = s->core->poll(ticket, &j);
+  if (rc == VP_ENOTFOUND) return set_error(VP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  if (rc != VP_OK) return rc;
+  res->status = j.status;
+  res->t_submit = j.t_submit;
+  res->t_admit = j.t_admit;
+  res->t_start = j.t_start;
+  res->t_done = j.t_done;
+  res->dev_first_tile = j.dev_start;
+  res->dev_last_tile = j.dev_done;
   return VP_OK;
 }
 
@@ -489,30 +481,9 @@ int vp_serve_stats(vp_ctx *ctx, uint64_t *launches, double *resident_ms) {
     *resident_ms = 0.0;
     return VP_OK;
   }
-  std::lock_guard<std::mutex> lk(s->mu);
-  *launches = s->launches;
-  *resident_ms = s->resident_ms;
-  return VP_OK;
-}
-
-int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res) {
-  if (!ctx || !res) return set_error(VP_EINVAL, "NULL context or result");
-  Scheduler *s = ctx->sched;
-  if (!s) return set_error(VP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->jobs.find(ticket);
-  if (it == s->jobs.end()) return set_error(VP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  JobRec *j = it->second;
-  if (j->state != kDone) return VP_EAGAIN;
-  res->status = j->status;
-  res->t_submit = j->t_submit;
-  res->t_admit = j->t_admit;
-  res->t_start = j->t_start;
-  res->t_done = j->t_done;
-  res->dev_first_tile = j->dev_start;
-  res->dev_last_tile = j->dev_done;
-  s->jobs.erase(it);
-  delete j;
+  std::lock_guard<std::mutex> lk(s->ex.stats_mu);
+  *launches = s->ex.launches;
+  *resident_ms = s->ex.resident_ms;
   return VP_OK;
 }
 
