@@ -122,41 +122,48 @@ struct TileArgs {
 };
 
 // ---------------------------------------------------------------------------
-// serving: a persistent kernel pulls (job slot, tile) items from a ring that
-// the host publishes in host-mapped memory.
+// serving: persistent kernels pull (job slot, tile) items from rings that the
+// host publishes in host-mapped memory.  Ring 0 holds table items and the
+// point/Gaussian pass's tiles; ring 1 the shapelet pass's tiles, published
+// once the job's point/Gaussian tiles are done.  One kernel per ring, each at
+// the occupancy of its own pass.
 // ---------------------------------------------------------------------------
 constexpr int kServeSlots = 1024;
 constexpr uint64_t kRingSize = 1ull << 20;
 constexpr uint64_t kNoClaim = ~0ull;
+constexpr int kServeRings = 2;
 
 struct ServeJobDesc {
   TileArgs a;            // tiling of the point/Gaussian pass (kPgChan-wide blocks)
   DeriveArgs da;         // table items (when the job builds its tables)
   FluxArgs fa;
-  int64_t ntiles;        // a.n_rb * a.n_cb
-  int64_t ntable;        // table items
-  uint64_t seq;          // sequence number of the tile phase (> 0, grows with publication)
+  int64_t ntiles;        // a.n_rb * a.n_cb (tiles of each pass)
+  int64_t ntable;        // table work units (kTileRows components or flux entries each)
+  int64_t per_pg, per_shp, per_table;  // consecutive tiles / table units behind one ring entry
+  uint64_t seq;          // sequence number of the point/Gaussian phase (> 0, grows with publication)
+  uint64_t seq_shp;      // sequence number of the shapelet phase
   uint64_t seq_table;    // sequence number of the table phase
-  uint64_t done_target;  // slot's tile counter value once this job's last tile is done
-  uint64_t table_target; // slot's table counter value once the last table item is done
+  uint64_t done_target;  // slot's entry counter value once the point/Gaussian phase is done
+  uint64_t shp_target;   // slot's entry counter value once the shapelet phase is done
+  uint64_t table_target; // slot's table counter value once the last table entry is done
 };
 
 struct ServeHost {       // host-mapped, coherent
-  uint64_t tail;         // tiles published (written by the host with release order)
+  uint64_t tail[kServeRings];  // items published per ring (written by the host with release order)
   uint64_t stop;         // non-zero: workers exit once idle
   uint64_t started[kServeSlots];   // seq of the job whose first tile has started
-  uint64_t finished[kServeSlots];  // seq of the job whose last tile has finished
+  uint64_t finished[kServeSlots];  // seq (or seq_shp) of the job phase whose last tile has finished
   uint64_t started_clk[kServeSlots];   // device wall clock when that first tile started
   uint64_t finished_clk[kServeSlots];  // device wall clock when that last tile finished
   uint64_t tabled[kServeSlots];    // seq_table of the job whose tables are built
-  uint64_t ring[kRingSize];        // (slot << 48) | (table item << 47) | item index
+  uint64_t ring[kServeRings][kRingSize];  // (slot << 48) | (table entry << 47) | entry index
   ServeJobDesc jobs[kServeSlots];
 };
 
 struct ServeDev {        // device memory
-  uint64_t head;         // items claimed
-  uint64_t tail_cache;   // largest published-item count any worker has read from the host
-  uint64_t quit_epoch;   // launch epoch whose workers are to exit
+  uint64_t head[kServeRings];        // items claimed per ring
+  uint64_t tail_cache[kServeRings];  // largest published-item count any worker has read from the host
+  uint64_t quit_epoch[kServeRings];  // launch epoch whose workers are to exit
   uint64_t done[kServeSlots];
   uint64_t tdone[kServeSlots];
 };
@@ -205,9 +212,9 @@ hipError_t launch_tiles_build(const TileBuildArgs &a, int max_nmax, hipStream_t 
 hipError_t launch_pg(const TileArgs &a, int prec, hipStream_t s);
 hipError_t launch_shp(const TileArgs &a, int prec, int max_nmax, hipStream_t s);
 hipError_t launch_lut_build(float *T, hipStream_t s);
-hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
+hipError_t launch_serve(int ring, ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
                         hipStream_t s);
-hipError_t serve_grid(int *grid);
+hipError_t serve_grid(int ring, int *grid);
 hipError_t launch_gain(const GainArgs &a, hipStream_t s);
 hipError_t launch_gain_subtract(const GainArgs &a, hipStream_t s);
 bool gain_supported(int n_ant);

@@ -1375,21 +1375,29 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(3))) 
 }
 
 // ---------------------------------------------------------------------------
-// serving: persistent kernel (continuous batching, mixed path)
+// serving: persistent kernels (continuous batching, mixed path)
 // ---------------------------------------------------------------------------
+// One kernel per ring.  Every workgroup loops: claim the next published entry
+// of its ring (compare-and-swap on a device counter), copy that job's
+// arguments from host-mapped memory into LDS, and run the entry's work with
+// the same device functions as the standalone kernels, so that a job's result
+// is the same alone and in a mix.  An entry stands for a run of consecutive
+// units of one job (the host sizes runs so that a job still spreads over every
+// workgroup): on ring 0, slices of the job's per-(sky, observation) tables or
+// point/Gaussian tiles; on ring 1, the shapelet pass of tiles (each tile's two
+// kShpChan-wide halves), which reads what the point/Gaussian tiles wrote.
+// Runs keep the claims (one device-wide atomic and two host-memory reads
+// each) far below the rate at which small tiles complete.  The passes live in separate kernels
+// because each runs at the occupancy of its own register budget (the
+// shapelet contraction needs twice the point/Gaussian pass's registers).
+// Entries are counted done per job slot; the last one of a phase publishes
+// the phase's sequence number to the host, which then publishes the next
+// phase.
+// A workgroup exits when any workgroup of the launch has found nothing to
+// claim for idle_ticks (all exit together, after their current item), or when
+// the host sets stop; no workgroup ever waits on another, and neither kernel
+// waits on the other.
 
-// Every workgroup loops: claim the next published item (compare-and-swap on
-// a device counter), copy that job's arguments from host-mapped memory into
-// LDS, and either build a slice of the job's per-(sky, observation) tables
-// (table item) or run the point/Gaussian tile and then its two shapelet
-// half-tiles with the same device functions as the standalone kernels (so a
-// job's result is the same alone and in a mix).  Items are counted done per
-// job slot; the last one of a phase publishes the phase's sequence number to
-// the host.  Building tables here rather than in separate kernels matters:
-// this kernel occupies every CU, so other kernels would wait for it to drain.  A workgroup exits
-// when any workgroup of the launch has found nothing to claim for idle_ticks
-// (all exit together, after their current item), or when the host sets stop;
-// no workgroup ever waits on another.
 // Kept out of line so that its FP64 library calls do not add to the register
 // allocation of the tile path that shares the kernel.
 __device__ __noinline__ void serve_table_item(const ServeJobDesc &job, int64_t item, int tid) {
@@ -1404,14 +1412,34 @@ __device__ __noinline__ void serve_table_item(const ServeJobDesc &job, int64_t i
   }
 }
 
-union ServeSmem {
+template <int RING>
+struct ServeSmem;
+template <>
+struct ServeSmem<0> {
   PgSmem<float> pg;
+};
+template <>
+struct ServeSmem<1> {
   ShpSmem<kCmBf16x3> shp;
 };
 
-__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_serve(ServeHost *H, ServeDev *D, uint64_t idle_ticks,
-                                                     uint64_t epoch) {
-  __shared__ ServeSmem sm;
+// A copy of a structure that every lane of the wave holds alike, read from
+// lane 0 word by word: the compiler then keeps it in scalar registers (a
+// structure loaded from LDS would otherwise occupy vector registers).
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T &x) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structure");
+  T r;
+  const uint32_t *src = (const uint32_t *)&x;
+  uint32_t *dst = (uint32_t *)&r;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return r;
+}
+
+template <int RING>
+__device__ __forceinline__ void serve_kernel(ServeHost *H, ServeDev *D, uint64_t idle_ticks, uint64_t epoch) {
+  __shared__ ServeSmem<RING> sm;
   __shared__ ServeJobDesc job;
   __shared__ uint64_t s_claim, s_entry, s_seen, s_cached_seq;
   __shared__ int s_cached_slot, s_cached_table, s_reload;
@@ -1426,7 +1454,7 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       const uint64_t t_idle = wall_clock64();
       unsigned backoff = 1;
       for (;;) {
-        if (__hip_atomic_load(&D->quit_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (__hip_atomic_load(&D->quit_epoch[RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
         // Relaxed, system-scope accesses: host-mapped memory is read uncached,
         // and the ring entry and job arguments are read through addresses that
         // depend on the claimed index, which orders them after the tail.  An
@@ -1434,27 +1462,30 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
         // away the component tables the other workgroups are streaming.
         // The host's tail is read over PCIe only when the device-side copy says
         // the ring is empty; claims themselves touch device memory only.
-        uint64_t h = __hip_atomic_load(&D->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t t = __hip_atomic_load(&D->tail_cache, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t h = __hip_atomic_load(&D->head[RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t t = __hip_atomic_load(&D->tail_cache[RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (h >= t) {
-          t = __hip_atomic_load(&H->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          if (t > h) __hip_atomic_fetch_max(&D->tail_cache, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          t = __hip_atomic_load(&H->tail[RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (t > h) __hip_atomic_fetch_max(&D->tail_cache[RING], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (h < t) {
-          if (__hip_atomic_compare_exchange_strong(&D->head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+          if (__hip_atomic_compare_exchange_strong(&D->head[RING], &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT)) {
             claimed = h;
             break;
           }
+          // another workgroup took it: step back briefly so that a burst of
+          // claims does not turn into a storm of failing ones
+          __builtin_amdgcn_s_sleep(2);
           continue;
         }
         if (__hip_atomic_load(&H->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-        if (__hip_atomic_load(&D->quit_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (__hip_atomic_load(&D->quit_epoch[RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
         if (wall_clock64() - t_idle > idle_ticks) {
           // the ring has been empty for idle_ticks: the whole launch exits
-          // (workers finish their current item first) so that the host can
-          // relaunch a full grid for the next job
-          __hip_atomic_store(&D->quit_epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // (workers finish their current item first) so that the other
+          // ring's kernel, queued behind this one, can run
+          __hip_atomic_store(&D->quit_epoch[RING], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
         for (unsigned i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(8);
@@ -1462,26 +1493,45 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       }
       s_claim = claimed;
       if (claimed != kNoClaim) {
-        const uint64_t e =
-            __hip_atomic_load(&H->ring[claimed & (kRingSize - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint64_t e = __hip_atomic_load(&H->ring[RING][claimed & (kRingSize - 1)], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_SYSTEM);
         s_entry = e;
-        // The job arguments in LDS are reused when the item belongs to the same
-        // slot and phase and the slot still carries the same sequence number
-        // (the host rewrites a slot only between jobs or phases, changing it).
+        // The job arguments in LDS are reused when the entry belongs to the
+        // same slot and phase and the slot still carries the same sequence
+        // number (the host rewrites a slot only between jobs or phases,
+        // changing it).  On ring 0, the first entry of a phase newer than any
+        // this workgroup has run drops cached lines that may predate its
+        // inputs: the tables its tiles read are built by table entries of this
+        // same launch, and buffers can be reallocated and rewritten while the
+        // kernel runs.  A phase's inputs are complete before it is published
+        // and sequence numbers grow with publication, so one invalidation per
+        // newer sequence number suffices.  Ring 1 needs none: a shapelet phase
+        // is published once its point/Gaussian tiles are done, which happens
+        // in a launch of ring 0's kernel that ended before this launch began
+        // (the two run one after the other on one stream), and the kernel
+        // boundary makes their writes and tables visible; its arguments are
+        // read from host memory, uncached.  Invalidating here would throw away
+        // the coefficient tiles that every workgroup of the XCD streams.
         const int slot = (int)(e >> 48), table = (int)((e >> 47) & 1);
-        const uint64_t *seqp = table ? &H->jobs[slot].seq_table : &H->jobs[slot].seq;
+        const uint64_t *seqp =
+            table ? &H->jobs[slot].seq_table : (RING == 0 ? &H->jobs[slot].seq : &H->jobs[slot].seq_shp);
         const uint64_t seq = __hip_atomic_load(seqp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         s_reload = !(slot == s_cached_slot && table == s_cached_table && seq == s_cached_seq);
         s_cached_slot = slot;
         s_cached_table = table;
         s_cached_seq = seq;
+        if (RING == 0 && seq > s_seen) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          s_seen = seq;
+        }
       }
     }
     __syncthreads();
     if (s_claim == kNoClaim) return;
     const int slot = (int)(s_entry >> 48);
-    const bool table_item = (s_entry >> 47) & 1;
-    const int64_t tile = (int64_t)(s_entry & ((1ull << 47) - 1));
+    const bool table_item = RING == 0 && ((s_entry >> 47) & 1);
+    const int64_t entry = (int64_t)(s_entry & ((1ull << 47) - 1));
+    const uint64_t item_seq = s_cached_seq;
     if (s_reload) {
       const uint64_t *src = (const uint64_t *)&H->jobs[slot];
       uint64_t *dst = (uint64_t *)&job;
@@ -1489,21 +1539,12 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       for (int i = tid; i < words; i += kTileRows)
         dst[i] = __hip_atomic_load(&src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    const uint64_t item_seq = table_item ? job.seq_table : job.seq;
-    if (tid == 0 && item_seq > s_seen) {
-      // First item of a phase newer than any this workgroup has run: drop
-      // cached lines that may predate its inputs (buffers and tables can be
-      // reallocated and rewritten while this kernel runs).  A phase's inputs
-      // are complete before it is published and sequence numbers grow with
-      // publication, so one invalidation per newer sequence number suffices.
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      s_seen = item_seq;
-    }
-    __syncthreads();
+    __syncthreads();  // the copy is spread over the waves: complete before any field is read
     if (table_item) {
-      // per-(sky, observation) tables: items [0, nder) derive kTileRows
+      // per-(sky, observation) tables: units [0, nder) derive kTileRows
       // components each, the rest compute kTileRows flux-table entries each
-      serve_table_item(job, tile, tid);
+      const int64_t u1 = min(job.ntable, (entry + 1) * job.per_table);
+      for (int64_t u = entry * job.per_table; u < u1; ++u) serve_table_item(job, u, tid);
       __syncthreads();
       if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
@@ -1514,35 +1555,51 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
       __syncthreads();
       continue;
     }
-    if (tid == 0 && tile == 0) {
-      // the job's first tile (tiles are claimed in order): its start time, then the flag
+    const TileArgs a = wave_uniform(job.a);
+    const int64_t per = RING == 0 ? job.per_pg : job.per_shp;
+    const int64_t t1 = min(job.ntiles, (entry + 1) * per);
+    if (RING == 0 && tid == 0 && entry == 0) {
+      // the job's first entry (entries are claimed in order): its start time, then the flag
       __hip_atomic_store(&H->started_clk[slot], wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(&H->started[slot], job.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    const int rb = (int)(tile % job.a.n_rb), cb = (int)(tile / job.a.n_rb);
-    if (job.a.uniform)
-      pg_tile<kMixed, true>(job.a, rb, cb, sm.pg);
-    else
-      pg_tile<kMixed>(job.a, rb, cb, sm.pg);
-    __syncthreads();  // the tile's point/Gaussian sums are visible to the whole workgroup
-    if (job.a.S > 0) {
-      shp_tile_bf<kCmBf16x3>(job.a, rb, 2 * cb, sm.shp);
-      shp_tile_bf<kCmBf16x3>(job.a, rb, 2 * cb + 1, sm.shp);
+    for (int64_t tile = entry * per; tile < t1; ++tile) {
+      const int rb = (int)(tile % a.n_rb), cb = (int)(tile / a.n_rb);
+      if constexpr (RING == 0) {
+        if (a.uniform)
+          pg_tile<kMixed, true>(a, rb, cb, sm.pg);
+        else
+          pg_tile<kMixed>(a, rb, cb, sm.pg);
+      } else {
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) shp_tile_bf<kCmBf16x3>(a, rb, 2 * cb + h, sm.shp);
+      }
+      __syncthreads();  // the tile's LDS is reused by the next one
     }
-    __syncthreads();
     if (tid == 0) {
-      // this tile's visibilities are written back to memory before the tile is
-      // counted; the job's last count therefore follows every tile's data, and
-      // the host flag follows the last count
+      // the entry's visibilities are written back to memory before the entry
+      // is counted; the phase's last count therefore follows every tile's
+      // data, and the host flag follows the last count
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system-scope release: write back, no invalidate
+      const uint64_t target = RING == 0 ? job.done_target : job.shp_target;
       const uint64_t old = __hip_atomic_fetch_add(&D->done[slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old + 1 == job.done_target) {
+      if (old + 1 == target) {
         __hip_atomic_store(&H->finished_clk[slot], wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&H->finished[slot], job.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&H->finished[slot], item_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
     __syncthreads();  // LDS (job, tiles) is reused by the next claim
   }
+}
+
+__global__ __launch_bounds__(kTileRows) void k_serve_pg(
+    ServeHost *H, ServeDev *D, uint64_t idle_ticks, uint64_t epoch) {
+  serve_kernel<0>(H, D, idle_ticks, epoch);
+}
+
+__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_serve_shp(
+    ServeHost *H, ServeDev *D, uint64_t idle_ticks, uint64_t epoch) {
+  serve_kernel<1>(H, D, idle_ticks, epoch);
 }
 
 // ---------------------------------------------------------------------------
@@ -1691,21 +1748,26 @@ hipError_t launch_lut_build(float *T, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t serve_grid(int *grid) {
+hipError_t serve_grid(int ring, int *grid) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve, kTileRows, 0);
+  if (e == hipSuccess)
+    e = ring == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve_pg, kTileRows, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve_shp, kTileRows, 0);
   if (e != hipSuccess) return e;
   *grid = cus * (per > 0 ? per : 1);
   return hipSuccess;
 }
 
-hipError_t launch_serve(ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
+hipError_t launch_serve(int ring, ServeHost *host_dev, ServeDev *dev, uint64_t idle_ticks, uint64_t epoch, int grid,
                         hipStream_t s) {
   hipError_t e = upload_tables();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_serve, dim3(grid), dim3(kTileRows), 0, s, host_dev, dev, idle_ticks, epoch);
+  if (ring == 0)
+    hipLaunchKernelGGL(k_serve_pg, dim3(grid), dim3(kTileRows), 0, s, host_dev, dev, idle_ticks, epoch);
+  else
+    hipLaunchKernelGGL(k_serve_shp, dim3(grid), dim3(kTileRows), 0, s, host_dev, dev, idle_ticks, epoch);
   return hipGetLastError();
 }
 

@@ -2,17 +2,22 @@
 //
 // The scheduling policy (FIFO admission by HBM footprint, tickets, the
 // scheduler thread) is ServeCore (serve_core.cpp); this file is its device
-// side.  Admission writes the job's arguments into a host-mapped slot and
-// appends its items to a host-mapped ring: first table items when the job's
-// (sky, observation) pair has no tables yet, then -- once the host sees the
-// tables built -- its visibility tiles.  A persistent kernel (k_serve) on its
-// own stream claims items from the ring as they appear, so jobs that arrive
-// while others run share the device tile by tile.  The kernel exits after a
-// short idle period; the scheduler relaunches it when items are waiting.
-// Completion is signalled per job through host-mapped flags.
+// side.  Admission writes the job's arguments into a host-mapped slot; the
+// job then runs in up to three phases, each published as items on a
+// host-mapped ring once the previous phase is seen done: table items when the
+// job's (sky, observation) pair has no tables yet, the point/Gaussian tiles
+// (both on ring 0), and the shapelet tiles (ring 1), which read what the
+// point/Gaussian tiles wrote.  Each ring has a persistent kernel (k_serve_pg,
+// k_serve_shp) that claims items as they appear, so jobs that arrive while
+// others run share the device tile by tile.  The two kernels are launched on
+// one stream, ring 0's first, each only when its ring holds items (or ring 1
+// is about to), and exit after a short idle period; the scheduler relaunches
+// them while items wait.  Completion is signalled per job through
+// host-mapped flags.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -45,20 +50,44 @@ static int check_job(vp_ctx *ctx, const vp_job *job) {
   return VP_OK;
 }
 
+// Units behind one ring entry.  Tiles: about four entries per workgroup of
+// the kernel for the job's whole phase (their costs vary), at most kMaxRun
+// tiles (so that jobs queued behind wait for runs of bounded length).  Table
+// units cost alike and little (a few microseconds each): kTableEntries
+// entries per phase, since every claim is a device-wide atomic and the claims
+// of a burst are served one after another.
+constexpr int64_t kMaxRun = 64;
+static int64_t run_length(int64_t units, int grid) {
+  return std::max<int64_t>(1, std::min<int64_t>(kMaxRun, units / (4 * (int64_t)std::max(grid, 1))));
+}
+constexpr int64_t kTableEntries = 64;
+static int64_t table_run_length(int64_t units) {
+  return std::max<int64_t>(1, (units + kTableEntries - 1) / kTableEntries);
+}
+static int64_t entries(int64_t units, int64_t run) { return (units + run - 1) / run; }
+
 static int64_t table_items(const vp_sky *sky, const vp_obs *obs) {
   const int64_t J = (int64_t)sky->P + sky->G + sky->S;
   return (J + kTileRows - 1) / kTileRows + (J * obs->Kpad + kTileRows - 1) / kTileRows;
 }
 
 // What the device side keeps per job.
+enum JobPhase { kPhTables = 0, kPhPg = 1, kPhShp = 2 };
+
 struct JobExt {
   vp_job job{};
   int slot = -1;
-  uint64_t seq = 0, seq_table = 0;
-  int64_t ntiles = 0, ntable = 0;
+  uint64_t seq = 0, seq_shp = 0, seq_table = 0;
+  int64_t ntiles = 0;                       // tiles of each pass
+  int64_t ntable = 0;                       // table units, when the job builds its tables
+  int64_t run_pg = 1, run_shp = 1, run_table = 1;  // units per ring entry
+  int64_t e_pg = 0, e_shp = 0, e_table = 0;        // ring entries per phase (e_table: once building)
+  int64_t e_table_max = 0;                  // table entries, should the job build its tables
   DerivedEntry *d = nullptr;
-  bool owner = false;      // this job builds the pair's tables
-  bool tiles_out = false;  // tiles published
+  bool owner = false;     // this job builds the pair's tables
+  bool shp = false;       // the job has a shapelet phase
+  int phase = kPhTables;  // the phase published last (kPhTables: tiles not yet published)
+  uint64_t ring_items(int r) const { return r == 0 ? (uint64_t)(e_pg + e_table) : (shp ? (uint64_t)e_shp : 0); }
 };
 
 static JobExt &ext(CoreJob &j) { return *(JobExt *)j.payload; }
@@ -71,16 +100,18 @@ class HipExecutor : public ServeExecutor {
   ServeDev *D = nullptr;
   std::vector<int> free_slots;
   std::vector<uint64_t> slot_target, slot_ttarget;
-  uint64_t tail = 0, ring_inflight = 0, next_seq = 1;
+  uint64_t tail[kServeRings] = {0, 0}, ring_inflight[kServeRings] = {0, 0}, next_seq = 1;
+  int shp_expected = 0;  // running jobs in their point/Gaussian phase with a shapelet phase to come
   hipStream_t kstream = nullptr, aux = nullptr;
-  hipEvent_t kev0 = nullptr, kev = nullptr;  // around each launch of the persistent kernel
+  hipEvent_t kev0 = nullptr, kev = nullptr;  // around each launch group
   bool launched = false;
-  uint64_t epoch = 0;  // launch counter; workers of a launch exit together
-  int grid = 0;
+  int group_kernels = 0;  // kernels in the launch group in flight
+  uint64_t epoch = 0;     // launch counter; workers of a launch exit together
+  int grid[kServeRings] = {0, 0};
   uint64_t idle_ticks = 0;
   std::mutex stats_mu;     // launches and resident_ms, read by vp_serve_stats
-  uint64_t launches = 0;   // completed launches
-  double resident_ms = 0;  // their total duration
+  uint64_t launches = 0;   // completed kernel launches
+  double resident_ms = 0;  // total duration of their launch groups
 
   int init(vp_ctx *c);
   void teardown();
@@ -98,8 +129,9 @@ class HipExecutor : public ServeExecutor {
   void retired(CoreJob &j) override;
 
  private:
-  void publish(int slot, int64_t n, bool table);
+  void publish(int ring, int slot, int64_t n, bool table);
   void publish_tiles(JobExt &x);
+  void publish_shp(JobExt &x);
   hipError_t reap_kernel();
 };
 
@@ -110,31 +142,48 @@ struct Scheduler {
 
 bool HipExecutor::has_room(const CoreJob &j) {
   const JobExt &x = *(const JobExt *)j.payload;
-  return !free_slots.empty() &&
-         ring_inflight + (uint64_t)x.ntiles + (uint64_t)table_items(x.job.sky, x.job.obs) <= kRingSize;
+  const uint64_t need1 = x.ring_items(1);
+  const uint64_t need0 = (uint64_t)(x.e_pg + x.e_table_max);  // at most
+  return !free_slots.empty() && ring_inflight[0] + need0 <= kRingSize && ring_inflight[1] + need1 <= kRingSize;
 }
 
-void HipExecutor::publish(int slot, int64_t n, bool table) {
+void HipExecutor::publish(int ring, int slot, int64_t n, bool table) {
   const uint64_t flag = table ? (1ull << 47) : 0ull;
   for (int64_t t = 0; t < n; ++t)
-    H->ring[(tail + (uint64_t)t) & (kRingSize - 1)] = ((uint64_t)slot << 48) | flag | (uint64_t)t;
-  tail += (uint64_t)n;
+    H->ring[ring][(tail[ring] + (uint64_t)t) & (kRingSize - 1)] = ((uint64_t)slot << 48) | flag | (uint64_t)t;
+  tail[ring] += (uint64_t)n;
   std::atomic_thread_fence(std::memory_order_release);
-  __atomic_store_n(&H->tail, tail, __ATOMIC_RELEASE);
+  __atomic_store_n(&H->tail[ring], tail[ring], __ATOMIC_RELEASE);
 }
 
-// Tile phase: the job's tables are ready; publish its tiles under a fresh
-// sequence number (workers acquire once per newer sequence number, which
-// makes the freshly built tables visible to them).
+// Point/Gaussian phase: the job's tables are ready; publish its tiles under a
+// fresh sequence number (workers acquire once per newer sequence number,
+// which makes the freshly built tables visible to them).
 void HipExecutor::publish_tiles(JobExt &x) {
   ServeJobDesc &desc = H->jobs[x.slot];
   x.seq = next_seq++;
-  slot_target[x.slot] += (uint64_t)x.ntiles;
+  slot_target[x.slot] += (uint64_t)x.e_pg;
   desc.seq = x.seq;
   desc.done_target = slot_target[x.slot];
   std::atomic_thread_fence(std::memory_order_release);
-  publish(x.slot, x.ntiles, false);
-  x.tiles_out = true;
+  publish(0, x.slot, x.e_pg, false);
+  x.phase = kPhPg;
+  if (x.shp) ++shp_expected;
+}
+
+// Shapelet phase: every point/Gaussian tile of the job is written back; its
+// shapelet tiles add to them (the newer sequence number makes the shapelet
+// kernel's workers drop cached lines of the visibilities).
+void HipExecutor::publish_shp(JobExt &x) {
+  ServeJobDesc &desc = H->jobs[x.slot];
+  x.seq_shp = next_seq++;
+  slot_target[x.slot] += (uint64_t)x.e_shp;
+  desc.seq_shp = x.seq_shp;
+  desc.shp_target = slot_target[x.slot];
+  std::atomic_thread_fence(std::memory_order_release);
+  publish(1, x.slot, x.e_shp, false);
+  x.phase = kPhShp;
+  --shp_expected;
 }
 
 int HipExecutor::admit(CoreJob &j) {
@@ -174,7 +223,9 @@ int HipExecutor::admit(CoreJob &j) {
   desc.a = a;
   desc.ntiles = x.ntiles;
   desc.ntable = 0;
-  ring_inflight += (uint64_t)x.ntiles;
+  desc.per_pg = x.run_pg;
+  desc.per_shp = x.run_shp;
+  desc.per_table = x.run_table;
   const int J = sky->P + sky->G + sky->S;
   if (build && J == 0) {
     derived_built(ctx, d);
@@ -184,25 +235,27 @@ int HipExecutor::admit(CoreJob &j) {
     // table phase: the persistent kernel builds the pair's tables
     x.owner = true;
     x.ntable = table_items(sky, obs);
+    x.e_table = x.e_table_max;
     x.seq_table = next_seq++;
-    slot_ttarget[slot] += (uint64_t)x.ntable;
+    slot_ttarget[slot] += (uint64_t)x.e_table;
     desc.da = make_derive_args(sky, obs, d->d);
     desc.fa = make_flux_args(sky, obs, d->d);
     desc.ntable = x.ntable;
     desc.seq_table = x.seq_table;
     desc.table_target = slot_ttarget[slot];
-    ring_inflight += (uint64_t)x.ntable;
     std::atomic_thread_fence(std::memory_order_release);
-    publish(slot, x.ntable, true);
+    publish(0, slot, x.e_table, true);
   } else if (derived_ready(ctx, d)) {
     publish_tiles(x);
   }
+  ring_inflight[0] += x.ring_items(0);
+  ring_inflight[1] += x.ring_items(1);
   return VP_OK;
 }
 
 bool HipExecutor::poll(CoreJob &j) {
   JobExt &x = ext(j);
-  if (!x.tiles_out) {
+  if (x.phase == kPhTables) {
     if (x.owner && __atomic_load_n(&H->tabled[x.slot], __ATOMIC_ACQUIRE) == x.seq_table) {
       derived_built(ctx, x.d);
       x.owner = false;
@@ -210,15 +263,22 @@ bool HipExecutor::poll(CoreJob &j) {
     if (!x.owner && derived_ready(ctx, x.d)) publish_tiles(x);
     return false;
   }
-  const uint64_t st = __atomic_load_n(&H->started[x.slot], __ATOMIC_ACQUIRE);
-  if (j.t_start == 0 && st == x.seq) {
+  if (j.t_start == 0 && __atomic_load_n(&H->started[x.slot], __ATOMIC_ACQUIRE) == x.seq) {
     timespec ts;
     clock_gettime(CLOCK_MONOTONIC, &ts);
     j.t_start = (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
     j.dev_start = __atomic_load_n(&H->started_clk[x.slot], __ATOMIC_RELAXED);
   }
   const uint64_t fin = __atomic_load_n(&H->finished[x.slot], __ATOMIC_ACQUIRE);
-  if (fin != x.seq) return false;
+  if (x.phase == kPhPg) {
+    if (fin != x.seq) return false;
+    if (x.shp) {
+      publish_shp(x);
+      return false;
+    }
+  } else if (fin != x.seq_shp) {
+    return false;
+  }
   if (j.dev_start == 0) j.dev_start = __atomic_load_n(&H->started_clk[x.slot], __ATOMIC_RELAXED);
   j.dev_done = __atomic_load_n(&H->finished_clk[x.slot], __ATOMIC_RELAXED);
   j.status = VP_OK;
@@ -227,7 +287,8 @@ bool HipExecutor::poll(CoreJob &j) {
 
 void HipExecutor::finished(CoreJob &j) {
   JobExt &x = ext(j);
-  ring_inflight -= (uint64_t)(x.ntiles + x.ntable);
+  ring_inflight[0] -= x.ring_items(0);
+  ring_inflight[1] -= x.ring_items(1);
   free_slots.push_back(x.slot);
   serve_release_derived(ctx, x.d);
 }
@@ -243,8 +304,8 @@ void HipExecutor::retired(CoreJob &j) {
   j.payload = nullptr;
 }
 
-// A finished launch of the persistent kernel is counted (launches, resident
-// time) and forgotten; hipErrorNotReady while it runs, its error if it failed.
+// A finished launch group is counted (kernel launches, resident time) and
+// forgotten; hipErrorNotReady while it runs, its error if it failed.
 hipError_t HipExecutor::reap_kernel() {
   if (!launched) return hipSuccess;
   hipError_t q = hipEventQuery(kev);
@@ -255,36 +316,49 @@ hipError_t HipExecutor::reap_kernel() {
   if (hipEventElapsedTime(&ms, kev0, kev) != hipSuccess) ms = 0.f;
   std::lock_guard<std::mutex> lk(stats_mu);
   resident_ms += ms;
-  launches += 1;
+  launches += (uint64_t)group_kernels;
   return hipSuccess;
 }
 
+// Launches, one after the other on the kernel stream, ring 0's kernel when its
+// ring holds unclaimed items and ring 1's when its ring does or a running
+// job's shapelet phase is about to be published (it is then usually published
+// while ring 0's kernel finishes).  Nothing is launched while a group runs.
 int HipExecutor::kick() {
   const hipError_t q = reap_kernel();
   if (q == hipErrorNotReady) return VP_OK;
   if (q != hipSuccess) return hip_error(q, "serving kernel");
-  uint64_t head = 0;
-  hipError_t e = hipMemcpyAsync(&head, &D->head, sizeof(head), hipMemcpyDeviceToHost, aux);
+  uint64_t head[kServeRings] = {0, 0};
+  hipError_t e = hipMemcpyAsync(head, D->head, sizeof(head), hipMemcpyDeviceToHost, aux);
   if (e == hipSuccess) e = hipStreamSynchronize(aux);
-  if (e != hipSuccess) return hip_error(e, "reading the serving queue head");
-  if (head >= tail) return VP_OK;
+  if (e != hipSuccess) return hip_error(e, "reading the serving queue heads");
+  const bool run0 = head[0] < tail[0];
+  const bool run1 = head[1] < tail[1] || (run0 && shp_expected > 0);
+  if (!run0 && !run1) return VP_OK;
+  group_kernels = 0;
   e = hipEventRecord(kev0, kstream);
-  if (e == hipSuccess) e = launch_serve(H_dev, D, idle_ticks, ++epoch, grid, kstream);
+  for (int r = 0; r < kServeRings && e == hipSuccess; ++r) {
+    if (!(r == 0 ? run0 : run1)) continue;
+    e = launch_serve(r, H_dev, D, idle_ticks, ++epoch, grid[r], kstream);
+    if (e == hipSuccess) ++group_kernels;
+  }
   if (e == hipSuccess) e = hipEventRecord(kev, kstream);
-  if (e != hipSuccess) return hip_error(e, "launching the serving kernel");
-  launched = true;
+  // a launch that was enqueued is waited for by the event even when a later
+  // call failed; the group counts as launched as soon as one kernel is
+  launched = group_kernels > 0 && e == hipSuccess;
+  if (e != hipSuccess) return hip_error(e, "launching the serving kernels");
   return VP_OK;
 }
 
 void HipExecutor::idle() {
-  // count a launch that exited while nothing ran; an error stays with the
-  // event and surfaces at the next kick()
+  // count a launch group that exited while nothing ran; an error stays with
+  // the event and surfaces at the next kick()
   if (launched && hipEventQuery(kev) == hipSuccess) (void)reap_kernel();
 }
 
-// The persistent kernel could not be launched, or its launch failed on the
+// The serving kernels could not be launched, or a launch failed on the
 // device: every running job ends with that error (their tiles share the
-// kernel).  No kernel runs now.  The items still in the ring are retired
+// kernels).  No kernel runs now.  The items still in the rings are retired
 // (head = tail) so that a later launch does not run them into buffers their
 // callers may have freed; tables that were to be built are dropped rather than
 // marked ready; each slot's completion targets are re-read from the device
@@ -292,11 +366,13 @@ void HipExecutor::idle() {
 // (a slot whose counters cannot be read stays out of use).
 void HipExecutor::abandon(const std::vector<CoreJob *> &running, int rc) {
   (void)rc;
+  if (launched) (void)hipEventSynchronize(kev);
+  (void)hipStreamSynchronize(kstream);
+  launched = false;
   bool synced = false;
   std::vector<uint64_t> done(kServeSlots), tdone(kServeSlots);
   {
-    const uint64_t t = tail;
-    hipError_t e = hipMemcpyAsync(&D->head, &t, sizeof(t), hipMemcpyHostToDevice, aux);
+    hipError_t e = hipMemcpyAsync(D->head, tail, sizeof(tail), hipMemcpyHostToDevice, aux);
     if (e == hipSuccess)
       e = hipMemcpyAsync(done.data(), D->done, sizeof(uint64_t) * kServeSlots, hipMemcpyDeviceToHost, aux);
     if (e == hipSuccess)
@@ -312,7 +388,9 @@ void HipExecutor::abandon(const std::vector<CoreJob *> &running, int rc) {
     if (ext(*j).owner) serve_abandon_derived(ctx, ext(*j).d);
   for (CoreJob *j : running) {
     JobExt &x = ext(*j);
-    ring_inflight -= (uint64_t)(x.ntiles + x.ntable);
+    ring_inflight[0] -= x.ring_items(0);
+    ring_inflight[1] -= x.ring_items(1);
+    if (x.phase == kPhPg && x.shp) --shp_expected;
     if (synced) {
       slot_target[x.slot] = done[x.slot];
       slot_ttarget[x.slot] = tdone[x.slot];
@@ -335,7 +413,7 @@ int HipExecutor::init(vp_ctx *c) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreate(&kev0);
   if (e == hipSuccess) e = hipEventCreate(&kev);
-  if (e == hipSuccess) e = serve_grid(&grid);
+  for (int r = 0; r < kServeRings && e == hipSuccess; ++r) e = serve_grid(r, &grid[r]);
   int rate_khz = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -344,9 +422,10 @@ int HipExecutor::init(vp_ctx *c) {
     teardown();
     return rc;
   }
-  // the workgroups exit together after 2 ms without work (the device is then
-  // free for other kernels); the scheduler relaunches when items wait
-  idle_ticks = (uint64_t)(rate_khz > 0 ? rate_khz : 100000) * 2;
+  // a launch's workgroups exit together after 100 us without work: the
+  // other ring's kernel, queued behind it, then runs (and the device is free
+  // for other kernels); the scheduler relaunches while items wait
+  idle_ticks = (uint64_t)(rate_khz > 0 ? rate_khz : 100000) / 10;
   slot_target.assign(kServeSlots, 0);
   slot_ttarget.assign(kServeSlots, 0);
   for (int i = kServeSlots - 1; i >= 0; --i) free_slots.push_back(i);
@@ -410,8 +489,6 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
                      (unsigned long long)ctx->budget);
   const int64_t ntiles = (int64_t)(((int64_t)job->obs->T * job->obs->B + kTileRows - 1) / kTileRows) *
                          (job->obs->Kpad / kPgChan);
-  if ((uint64_t)ntiles + (uint64_t)table_items(job->sky, job->obs) > kRingSize || ntiles >= ((int64_t)1 << 47))
-    return set_error(VP_ECAPACITY, "job has %lld tiles, more than the serving ring holds", (long long)ntiles);
   Scheduler *s = nullptr;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -426,13 +503,29 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
       ctx->sched = n;
     }
     s = ctx->sched;
-    // the job holds its sky and observation from here until it retires
-    const_cast<vp_sky *>(job->sky)->jobs += 1;
-    const_cast<vp_obs *>(job->obs)->jobs += 1;
   }
   JobExt *x = new JobExt();
   x->job = *job;
   x->ntiles = ntiles;
+  x->shp = job->sky->S > 0;
+  x->run_pg = run_length(ntiles, s->ex.grid[0]);
+  x->run_shp = run_length(ntiles, s->ex.grid[1]);
+  x->e_pg = entries(ntiles, x->run_pg);
+  x->e_shp = entries(ntiles, x->run_shp);
+  const int64_t tunits = table_items(job->sky, job->obs);
+  x->run_table = table_run_length(tunits);
+  x->e_table_max = entries(tunits, x->run_table);
+  if ((uint64_t)(x->e_pg + x->e_table_max) > kRingSize || (uint64_t)x->e_shp > kRingSize ||
+      ntiles >= ((int64_t)1 << 40)) {
+    delete x;
+    return set_error(VP_ECAPACITY, "job has %lld tiles, more than the serving ring holds", (long long)ntiles);
+  }
+  {
+    // the job holds its sky and observation from here until it retires
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const_cast<vp_sky *>(job->sky)->jobs += 1;
+    const_cast<vp_obs *>(job->obs)->jobs += 1;
+  }
   if (x->job.t_arrival_ns == 0) {
     timespec ts;
     clock_gettime(CLOCK_MONOTONIC, &ts);
