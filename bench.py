@@ -36,7 +36,15 @@ The JSON line carries:
                   noise): the sources peeled one after another with
                   calibration (Sec. 5.1) on the mixed path; time per source
                   split into prediction and gain solve, and the residual RMS
-                  against plain (uncalibrated) subtraction.
+                  against plain (uncalibrated) subtraction;
+  large_peel   -- the same observation with N(0, 1 Jy) data: the 10 sources
+                  subtracted one after another (vp_subtract) and the whole sky
+                  predicted, on the mixed path (complex64) and the FP64 path
+                  (complex128), with RMS(R_gpu - R_ref) beside RMS(R_ref) on
+                  sampled rows;
+  serving      -- the serving stream: p50/p99 latency, throughput, and the
+                  persistent kernel's resident time against the same jobs
+                  run back to back.
 """
 from __future__ import annotations
 
@@ -429,6 +437,97 @@ def paper_peel(n_iter=10, check=((14, 383), (0, 0), (7, 191))):
     return res
 
 
+def large_peel(check_rows=64, full_rows=4, reps=3):
+    """Workload 4 (12.5M visibilities): the 10 bright shapelets subtracted one
+    after another from resident N(0, 1 Jy) data, on the mixed path (complex64)
+    and the FP64 path (complex128), and the whole sky (100000 points, 5000
+    Gaussians, 10 shapelets) predicted on both.  The residual R = D - sum_k
+    V_k is checked on sampled rows against the oracle's: RMS(R_gpu - R_ref)
+    beside RMS(R_ref), and the error relative to the peeled flux; the full-sky
+    prediction likewise on fewer rows (the oracle's cost)."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2005_09316_amd import vp
+
+    obs, sky = synth.make_config(4)
+    nrows, K = obs.n_time * obs.n_bl, obs.n_chan
+    rng = np.random.default_rng(4400)
+    rows = np.sort(rng.choice(nrows, check_rows, replace=False))
+    frows = rows[:full_rows]
+    data = synth.noise_c64((nrows, K), seed=4401)
+    shp_sky = synth.select_components(sky, points=[], gauss=[], shapelets=None)
+    t0 = time.perf_counter()
+    r_ref = data[rows].astype(np.complex128) - oracle.predict(obs, shp_sky, rows=rows)
+    v_full_ref = oracle.predict(obs, sky, rows=frows)
+    t_oracle = time.perf_counter() - t0
+    ctx = vp.vp_create_ctx(0, 0)
+    oh = vp.vp_create_obs(ctx, obs)
+    peel = [vp.vp_create_sky(ctx, synth.select_components(sky, points=[], gauss=[], shapelets=[k]))
+            for k in range(sky.n_shp)]
+    full = vp.vp_create_sky(ctx, sky)
+    stream = torch.cuda.current_stream()
+    rsel = torch.as_tensor(rows, device="cuda")
+    res = {"n_vis": obs.n_vis, "n_sources": sky.n_shp, "check_rows": int(rows.size), "full_sky_check_rows": int(frows.size),
+           "oracle_s": round(t_oracle, 2)}
+    for name, prec, dtype, tdt in (("mixed", vp.VP_PREC_MIXED, vp.VP_C64, torch.complex64),
+                                   ("fp64", vp.VP_PREC_FP64, vp.VP_C128, torch.complex128)):
+        d0 = torch.from_numpy(data).to("cuda").to(tdt)
+        d = d0.clone()
+
+        def subtract_all():
+            for h in peel:
+                vp.vp_subtract(ctx, h, oh, prec, dtype, d.data_ptr(), stream.cuda_stream)
+
+        subtract_all()  # warm: tables
+        ms_sub = []
+        for _ in range(reps):
+            d.copy_(d0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            subtract_all()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_sub.append(e0.elapsed_time(e1))
+        got = d[rsel].cpu().numpy().astype(np.complex128)
+        diff = got - r_ref
+        out = torch.empty((nrows, K), dtype=tdt, device="cuda")
+        vp.vp_predict(ctx, full, oh, prec, dtype, out.data_ptr(), stream.cuda_stream)  # warm
+        ms_full = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vp.vp_predict(ctx, full, oh, prec, dtype, out.data_ptr(), stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_full.append(e0.elapsed_time(e1))
+        vf = out[torch.as_tensor(frows, device="cuda")].cpu().numpy().astype(np.complex128)
+        res[name] = {
+            "output": "complex64" if dtype == vp.VP_C64 else "complex128",
+            "ms_10_subtractions": round(min(ms_sub), 3),
+            "rms_residual_diff_jy": float(np.sqrt(np.mean(np.abs(diff) ** 2))),
+            "rms_residual_ref_jy": float(np.sqrt(np.mean(np.abs(r_ref) ** 2))),
+            "residual_err_vs_peeled_flux": oracle.error_metric(got, r_ref, obs, shp_sky),
+            "ms_full_sky_predict": round(min(ms_full), 3),
+            "full_sky_evals_per_s": obs.n_vis * sky.nominal_components() / (min(ms_full) * 1e-3),
+            "full_sky_err_vs_total_flux": oracle.error_metric(vf, v_full_ref, obs, sky),
+        }
+        _log("large peel (%s): 10 subtractions %.2f ms, rms(R_gpu - R_ref) %.3e Jy of rms(R_ref) %.3f Jy, "
+             "error / peeled flux %.2e; full sky %.2f ms (%.3e evals/s), error / total flux %.2e"
+             % (name, res[name]["ms_10_subtractions"], res[name]["rms_residual_diff_jy"],
+                res[name]["rms_residual_ref_jy"], res[name]["residual_err_vs_peeled_flux"],
+                res[name]["ms_full_sky_predict"], res[name]["full_sky_evals_per_s"],
+                res[name]["full_sky_err_vs_total_flux"]))
+        del d0, d, out
+        torch.cuda.empty_cache()
+    for h in peel + [full]:
+        vp.vp_destroy_sky(h)
+    vp.vp_destroy_obs(oh)
+    vp.vp_destroy_ctx(ctx)
+    return res
+
+
 def _pg_source_hash():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2005_09316_amd", "csrc", "vp_kernels.hip")).read()
@@ -651,6 +750,8 @@ def main():
     ap.add_argument("--no-peel", action="store_true", help="skip the calibrated-peel leg")
     ap.add_argument("--only-peel", action="store_true", help="run the calibrated-peel leg alone")
     ap.add_argument("--no-paper-peel", action="store_true", help="skip the paper-scale calibrated peel")
+    ap.add_argument("--no-large-peel", action="store_true", help="skip the large-peel subtraction leg")
+    ap.add_argument("--only-large-peel", action="store_true", help="run the large-peel subtraction leg alone")
     ap.add_argument("--only-paper-peel", action="store_true", help="run the paper-scale calibrated peel alone")
     ap.add_argument("--only-shapelets", action="store_true",
                     help="run only the shapelet-contraction leg and print its JSON")
@@ -676,6 +777,9 @@ def main():
         return
     if args.only_cpu_plan:
         print(json.dumps(cpu_plan(None, None)), flush=True)
+        return
+    if args.only_large_peel:
+        print(json.dumps(large_peel()), flush=True)
         return
     if args.only_paper_peel:
         print(json.dumps(paper_peel()), flush=True)
@@ -790,6 +894,7 @@ def main():
     trunc = None if args.no_truncation else truncation_sweep()
     peel = None if args.no_peel else calibrated_peel()
     ppeel = None if args.no_paper_peel else paper_peel()
+    lpeel = None if args.no_large_peel else large_peel()
 
     serving = None
     if not args.no_serve:
@@ -816,6 +921,7 @@ def main():
         "truncation_sweep": trunc,
         "calibrated_peel": peel,
         "paper_peel": ppeel,
+        "large_peel": lpeel,
     }
     print(json.dumps(line), flush=True)
 
