@@ -724,6 +724,9 @@ def paper_cost_comparison():
         vp.vp_destroy_sky(sh)
     for pname in ("mixed", "fp64"):
         res["shapelet_over_clean_%s" % pname] = res["shapelet_%s_ms" % pname] / res["clean_%s_ms" % pname]
+    # what the paper states for the same comparison, on its hardware (Sec. 5.3)
+    res["paper"] = {"shapelet_over_clean": "> 2", "hardware": "NVIDIA GeForce GTX 1080 Ti (12 GB)",
+                    "simulator": "the authors' CUDA simulator", "absolute_times": "not stated"}
     vp.vp_destroy_obs(oh)
     vp.vp_destroy_ctx(ctx)
     _log("paper cost comparison: %s" % json.dumps(res))

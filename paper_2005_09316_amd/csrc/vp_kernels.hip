@@ -1469,14 +1469,17 @@ __device__ __forceinline__ void serve_kernel(ServeHost *H, ServeDev *D, uint64_t
           if (t > h) __hip_atomic_fetch_max(&D->tail_cache[RING], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (h < t) {
-          if (__hip_atomic_compare_exchange_strong(&D->head[RING], &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT)) {
+          // a failed compare-and-swap returns the current head: try the next
+          // entry at once while entries remain
+          bool ok;
+          do {
+            ok = __hip_atomic_compare_exchange_strong(&D->head[RING], &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+          } while (!ok && h < t);
+          if (ok) {
             claimed = h;
             break;
           }
-          // another workgroup took it: step back briefly so that a burst of
-          // claims does not turn into a storm of failing ones
-          __builtin_amdgcn_s_sleep(2);
           continue;
         }
         if (__hip_atomic_load(&H->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
