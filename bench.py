@@ -662,8 +662,27 @@ def serve_stream(n_requests, rate_hz, budget_bytes):
                 evals += r.obs.n_vis * r.sky.nominal_components()
         time.sleep(0.0002)
     wall = (max(done_t) - start) / 1e9
-    time.sleep(0.05)  # the persistent kernel's idle exit, so that its last launch is counted
+    time.sleep(0.05)  # the persistent kernels' idle exit, so that their last launch is counted
     launches, resident_ms = vp.vp_serve_stats(ctx)
+    # 8 requests spread over the stream against the oracle, on 16 sampled rows
+    # each (a subtract request's data are the same seeded device noise again)
+    import oracle
+    check_errs = []
+    for i in np.linspace(0, len(prepared) - 1, 8).astype(int):
+        r, oh, sh, buf = prepared[i]
+        nrows = r.obs.n_time * r.obs.n_bl
+        rows = np.sort(np.random.default_rng(7000 + int(i)).choice(nrows, min(16, nrows), replace=False))
+        sel = torch.as_tensor(rows, device="cuda")
+        got = buf.reshape(nrows, r.obs.n_chan)[sel].cpu().numpy().astype(np.complex128)
+        ref = oracle.predict(r.obs, r.sky, rows=rows)
+        if r.kind == "subtract":
+            g = torch.Generator(device="cuda").manual_seed(r.noise_seed)
+            d0 = torch.randn(buf.shape, dtype=torch.complex64, device="cuda", generator=g)
+            ref = d0.reshape(nrows, r.obs.n_chan)[sel].cpu().numpy().astype(np.complex128) - ref
+            del d0
+        check_errs.append(oracle.error_metric(got, ref, r.obs, r.sky) if r.sky.nominal_components() else 0.0)
+    _log("serving: 8 requests against the oracle on 16 rows each, max error / total flux %.2e"
+         % max(check_errs))
     # the same requests back to back through vp_predict / vp_subtract, for the
     # serving efficiency
     stream = torch.cuda.current_stream()
@@ -685,7 +704,9 @@ def serve_stream(n_requests, rate_hz, budget_bytes):
            "evals_per_s": evals / wall, "precision": "mixed", "output": "complex64",
            "back_to_back_evals_per_s": evals / standalone, "back_to_back_s": standalone,
            "kernel_launches": launches, "kernel_resident_s": resident_ms / 1e3,
-           "resident_over_back_to_back": resident_ms / 1e3 / standalone}
+           "resident_over_back_to_back": resident_ms / 1e3 / standalone,
+           "oracle_check": {"requests": 8, "rows_each": 16, "max_err_vs_oracle": max(check_errs),
+                            "gate": 1e-6}}
     _log("serving: p50 %.1f ms, p99 %.1f ms, %.2e evals/s over %.1f s; persistent kernel %d launches, "
          "resident %.2f s against %.2f s back to back" % (out["p50_ms"], out["p99_ms"], out["evals_per_s"], wall,
                                                        launches, resident_ms / 1e3, standalone))
