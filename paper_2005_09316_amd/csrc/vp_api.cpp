@@ -1,6 +1,7 @@
 // vp_api.cpp -- C ABI of libvp: contexts, observations, sky models, predict
 // and subtract.  Serving (vp_submit / vp_poll) lives in vp_serve.cpp.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -281,6 +282,9 @@ void drop_all_derived(vp_ctx *ctx) {
 // ---------------------------------------------------------------------------
 // profiling
 // ---------------------------------------------------------------------------
+
+TraceRange::TraceRange(const char *name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
 
 ProfScope::ProfScope(vp_ctx *c, hipStream_t s, int k) : ctx(c), stream(s), kind(k) {
   if (ctx && ctx->profile) {
@@ -711,6 +715,7 @@ int vp_destroy_sky(vp_sky *sky) {
 
 int vp_predict(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis_dev,
                void *hip_stream) {
+  TraceRange tr("vp_predict");
   int rc = check_call(ctx, sky, obs, precision, dtype, vis_dev);
   if (rc != VP_OK) return rc;
   DeviceGuard g(ctx->device);
@@ -720,6 +725,7 @@ int vp_predict(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision,
 
 int vp_predict_noalloc(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *vis_dev,
                        void *hip_stream) {
+  TraceRange tr("vp_predict_noalloc");
   int rc = check_call(ctx, sky, obs, precision, dtype, vis_dev);
   if (rc != VP_OK) return rc;
   if (precision == VP_PREC_LUT)
@@ -760,6 +766,7 @@ int vp_predict_noalloc(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int pr
 
 int vp_subtract(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, int precision, int dtype, void *data_dev,
                 void *hip_stream) {
+  TraceRange tr("vp_subtract");
   int rc = check_call(ctx, sky, obs, precision, dtype, data_dev);
   if (rc != VP_OK) return rc;
   DeviceGuard g(ctx->device);

@@ -1566,8 +1566,11 @@ __device__ __forceinline__ void serve_kernel(ServeHost *H, ServeDev *D, uint64_t
       __hip_atomic_store(&H->started_clk[slot], wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(&H->started[slot], job.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    for (int64_t tile = entry * per; tile < t1; ++tile) {
-      const int rb = (int)(tile % a.n_rb), cb = (int)(tile / a.n_rb);
+    // tile t covers row block t mod n_rb and channel block t / n_rb; the
+    // run's blocks are stepped, not divided out per tile
+    const int64_t t0 = entry * per;
+    int rb = (int)(t0 % a.n_rb), cb = (int)(t0 / a.n_rb);
+    for (int64_t tile = t0; tile < t1; ++tile) {
       if constexpr (RING == 0) {
         if (a.uniform)
           pg_tile<kMixed, true>(a, rb, cb, sm.pg);
@@ -1578,6 +1581,10 @@ __device__ __forceinline__ void serve_kernel(ServeHost *H, ServeDev *D, uint64_t
         for (int h = 0; h < 2; ++h) shp_tile_bf<kCmBf16x3>(a, rb, 2 * cb + h, sm.shp);
       }
       __syncthreads();  // the tile's LDS is reused by the next one
+      if (++rb == a.n_rb) {
+        rb = 0;
+        ++cb;
+      }
     }
     if (tid == 0) {
       // the entry's visibilities are written back to memory before the entry

@@ -70,6 +70,15 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// A named range on the host timeline (roctx) for the lifetime of the guard;
+// rocprofv3 --marker-trace records it, and without a profiler it costs a call.
+struct TraceRange {
+  explicit TraceRange(const char *name);
+  ~TraceRange();
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // Selects a HIP device for the lifetime of the guard, restoring the previous one.
 struct DeviceGuard {
   int prev = 0;

@@ -17,6 +17,7 @@ extern "C" {
 int vp_peel(vp_ctx *ctx, const vp_sky *sky, const vp_obs *obs, const int32_t *ant1, const int32_t *ant2,
             int32_t n_ant, int32_t n_iter, int precision, int dtype, void *data_dev, void *gains_dev,
             void *hip_stream) {
+  TraceRange tr("vp_peel");
   int rc = check_call(ctx, sky, obs, precision, dtype, data_dev);
   if (rc != VP_OK) return rc;
   if (!ant1 || !ant2) return set_error(VP_EINVAL, "NULL tile arrays");

@@ -335,6 +335,7 @@ int HipExecutor::kick() {
   const bool run0 = head[0] < tail[0];
   const bool run1 = head[1] < tail[1] || (run0 && shp_expected > 0);
   if (!run0 && !run1) return VP_OK;
+  TraceRange tr(run0 ? (run1 ? "vp_serve launch: rings 0, 1" : "vp_serve launch: ring 0") : "vp_serve launch: ring 1");
   group_kernels = 0;
   e = hipEventRecord(kev0, kstream);
   for (int r = 0; r < kServeRings && e == hipSuccess; ++r) {
@@ -480,6 +481,7 @@ int vp_job_footprint(vp_ctx *ctx, const vp_job *job, uint64_t *bytes) {
 }
 
 int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
+  TraceRange tr("vp_submit");
   if (!ticket) return set_error(VP_EINVAL, "NULL ticket");
   int rc = check_job(ctx, job);
   if (rc != VP_OK) return rc;

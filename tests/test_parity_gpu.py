@@ -109,13 +109,19 @@ def test_predict_matches_oracle(ctx, name, prec, dtype):
 @pytest.mark.parametrize("name", ["tiny", "fornax-mid", "nmax-limit"])
 @pytest.mark.parametrize("prec", [vp.VP_PREC_FP32, vp.VP_PREC_MIXED_BF16X2])
 def test_reported_paths(ctx, name, prec):
-    """FP32-only and 2-way BF16 contraction paths: error reported, not gated."""
+    """FP32-only and 2-way BF16 contraction paths: their error is reported,
+    not held to the 1e-6 target.  The bound here only catches a broken path
+    (a dropped term, a wrong sign or index errs by O(1) of the total flux):
+    the arithmetic of these paths (FP32 recurrences and sums; a second-axis
+    value carried in two BF16 parts, 2^-17 relative) measured at most 1.5e-4
+    of the total flux over every Fornax-like visibility."""
     obs, sky, ref = _ref(name)
     with Handles(ctx, obs, sky) as h:
         got = run(ctx, h.obs, h.sky, obs, prec, vp.VP_C64)
     err = oracle.error_metric(got, ref, obs, sky)
-    _log("precision %d, case %s: error / total flux = %.3e (not gated)" % (prec, name, err))
+    _log("precision %d, case %s: error / total flux = %.3e (reported)" % (prec, name, err))
     assert np.all(np.isfinite(got))
+    assert err <= 1e-3
 
 
 @pytest.mark.parametrize("prec,dtype", [(vp.VP_PREC_FP64, vp.VP_C128), (vp.VP_PREC_MIXED, vp.VP_C64)])

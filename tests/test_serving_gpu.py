@@ -269,21 +269,26 @@ def test_error_paths(ctx):
 
 
 def test_destroy_busy_context():
+    """A context with pending jobs refuses to go (VP_EBUSY) and goes once they
+    are collected.  16 jobs of ~1 ms of device work each are pending when
+    destroy is attempted microseconds after the last submission."""
     import torch
     obs, sky = synth.make_config(1, seed=79, n_tiles=64, n_time=4, n_chan=32, n_point=3000, n_gauss=100,
                                  shapelet_nmax=[40])
     ctx = vp.vp_create_ctx(0, 0)
     oh, sh = vp.vp_create_obs(ctx, obs), vp.vp_create_sky(ctx, sky)
-    b = vis_tensor(obs, vp.VP_C64)
+    bufs = [vis_tensor(obs, vp.VP_C64) for _ in range(16)]
     torch.cuda.synchronize()
     tickets = [vp.vp_submit(ctx, vp.VP_JOB_PREDICT, sh, oh, vp.VP_PREC_MIXED, vp.VP_C64, b.data_ptr())
-               for _ in range(4)]
-    busy = False
-    try:
+               for b in bufs]
+    with pytest.raises(vp.VPError) as e:
         vp.vp_destroy_ctx(ctx)
-    except vp.VPError as e:
-        busy = e.code == vp.VP_EBUSY
-    if not busy:
-        pytest.skip("jobs finished before destroy was attempted")
-    _wait(ctx, tickets)
+    assert e.value.code == vp.VP_EBUSY
+    with pytest.raises(vp.VPError) as e:
+        vp.vp_destroy_sky(sh)
+    assert e.value.code == vp.VP_EBUSY
+    res = _wait(ctx, tickets)
+    assert all(r["status"] == vp.VP_OK for r in res.values())
+    vp.vp_destroy_sky(sh)
+    vp.vp_destroy_obs(oh)
     vp.vp_destroy_ctx(ctx)
