@@ -42,9 +42,11 @@ The JSON line carries:
                   predicted, on the mixed path (complex64) and the FP64 path
                   (complex128), with RMS(R_gpu - R_ref) beside RMS(R_ref) on
                   sampled rows;
-  serving      -- the serving stream: p50/p99 latency, throughput, and the
-                  persistent kernel's resident time against the same jobs
-                  run back to back.
+  serving      -- the serving stream: p50/p99 latency, throughput, the
+                  persistent kernels' resident time against the same jobs
+                  run back to back, and 8 requests checked against the
+                  oracle; serving_full_hbm_budget repeats it with the
+                  budget at 90% of free device memory.
 """
 from __future__ import annotations
 
