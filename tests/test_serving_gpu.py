@@ -55,6 +55,15 @@ def _job_specs():
         if kind == vp.VP_JOB_SUBTRACT:
             data = synth.noise_c64((obs.n_time, obs.n_bl, obs.n_chan), seed=900 + i)
         specs.append((obs, sky, kind, dtype, data))
+    # the phases' edge cases: shapelets alone (the point/Gaussian phase only
+    # clears or passes the buffer), and points and Gaussians alone (no
+    # shapelet phase), each as a predict and a subtract
+    for i, (npt, ng, nmax) in enumerate(((0, 0, [44, 17]), (250, 30, []))):
+        obs, sky = synth.make_config(1, seed=530 + i, n_tiles=24, n_time=2, n_chan=11, n_point=npt, n_gauss=ng,
+                                     shapelet_nmax=nmax)
+        specs.append((obs, sky, vp.VP_JOB_PREDICT, vp.VP_C64, None))
+        specs.append((obs, sky, vp.VP_JOB_SUBTRACT, vp.VP_C128,
+                      synth.noise_c64((obs.n_time, obs.n_bl, obs.n_chan), seed=940 + i)))
     return specs
 
 
@@ -98,7 +107,10 @@ def test_mix_equals_alone_and_oracle(ctx):
         assert err <= 1e-6, (i, err)
         r = res[tickets[i]]
         assert r["t_submit"] <= r["t_admit"] <= r["t_start"] <= r["t_done"]
-    _log("10 uneven jobs: mix == alone bitwise, all within 1e-6 of the oracle")
+    _log("%d uneven jobs: mix == alone bitwise, all within 1e-6 of the oracle" % len(specs))
+    launches, resident_ms = vp.vp_serve_stats(ctx)
+    _log("  persistent kernels: %d launches, %.2f ms resident" % (launches, resident_ms))
+    assert launches >= 2 and resident_ms > 0  # both passes ran at least once
     pairs = _overlapping_pairs([res[t] for t in tickets])
     _log("  %d pairs of jobs had tiles on the device at the same time" % pairs)
     assert pairs > 0
