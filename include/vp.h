@@ -228,16 +228,20 @@ typedef struct {
 /* Enqueue a job; returns a ticket.  The caller's writes to job->vis_dev (the
  * data of a subtract job) must be complete, i.e. the writing stream
  * synchronised, before the call.  Only VP_PREC_MIXED is served: the
- * persistent kernel that runs every admitted job's tiles is one compiled
- * instance of the mixed path, and its register use sets the occupancy that
- * all jobs share (an FP64 instance beside it would run at lower occupancy and
- * serialise against it); FP64 work goes through vp_predict / vp_subtract on a
- * caller stream, which may run beside serving.  The job is
- * admitted when its HBM footprint
- * fits the budget minus what admitted jobs hold, in FIFO order; admitted jobs
- * are expanded into tiles that a persistent device kernel processes together
- * with the tiles of other admitted jobs.  Errors: VP_EINVAL, VP_ECAPACITY if
- * the footprint exceeds the whole budget.  Thread-safe. */
+ * persistent kernels that run every admitted job's tiles are compiled
+ * instances of the mixed path, and their register use sets the occupancy
+ * that all jobs share (FP64 instances beside them would run at lower
+ * occupancy and serialise against them); FP64 work goes through vp_predict /
+ * vp_subtract on a caller stream, which may run beside serving.  The job is
+ * admitted when its HBM footprint fits the budget minus what admitted jobs
+ * hold, in FIFO order, and a job slot and ring space are free; an admitted
+ * job's tiles (its tables first, when its sky and observation have none yet)
+ * are run by two persistent device kernels, one for the point/Gaussian pass
+ * and one for the shapelet pass, together with the tiles of other admitted
+ * jobs.  A failure of the job's own admission (e.g. its table allocation)
+ * ends that job alone; a device failure ends every running job.  Errors:
+ * VP_EINVAL, VP_ECAPACITY if the footprint exceeds the whole budget or the job
+ * has more tiles than a serving ring holds.  Thread-safe. */
 int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket);
 
 /* Non-blocking: VP_OK with *res filled when the job is done (res->status holds
@@ -247,10 +251,10 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket);
 int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res);
 
 /* Serving measurement: the number of completed launches of the persistent
- * serving kernel since the context's first vp_submit and their total
- * duration in ms (HIP events around each launch on the kernel's stream; a
- * launch still running is not counted).  Zeros before the first vp_submit.
- * Errors: VP_EINVAL. */
+ * serving kernels since the context's first vp_submit and the total duration
+ * in ms of their launch groups (HIP events around each group on the kernels'
+ * stream; a group still running is not counted).  Zeros before the first
+ * vp_submit.  Errors: VP_EINVAL. */
 int vp_serve_stats(vp_ctx *ctx, uint64_t *launches, double *resident_ms);
 
 /* HBM footprint (bytes) that admission charges for `job`.  Errors: VP_EINVAL. */

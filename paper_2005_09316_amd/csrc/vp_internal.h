@@ -33,7 +33,9 @@ constexpr int kPairsMax = (kNmaxLimit / 32 + 1) * (kNmaxLimit / 32 + 2) / 2;
 constexpr int kA32PerPair = 2 * 8 * 64;  // floats: [parity][K step of 2 orders][lane]
 constexpr int kAbfPerPair = 2 * 64 * 8;  // BF16 values of one split part: [parity][lane][8]
 
-enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4, kMixedF32Mma = 5, kLut = 6 };
+// Precision paths, numbered as VP_PREC_*; 5 (the FP32-MFMA contraction of the
+// mixed path) is retired and refused at the boundary.
+enum Prec : int { kFP64 = 0, kMixed = 1, kMixedBf16 = 2, kFP32 = 3, kMixedBf16x2 = 4, kLut = 6 };
 
 // Lookup table of the basis (the lookup-table variant): kLutSamples + 2 rows
 // of kLutStride FP32 values.
