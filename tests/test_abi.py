@@ -53,6 +53,24 @@ def test_null_arguments_are_rejected_before_any_device_work():
     assert "NULL" in vp.vp_last_error()
 
 
+def test_other_entry_points_reject_null_arguments_before_any_device_work():
+    """Every remaining entry point checks its handles and out-parameters
+    first: the serving calls, subtract, destroy and the profiling calls."""
+    import ctypes
+    lib = vp.load()
+    ticket = ctypes.c_uint64(0)
+    assert lib.vp_submit(None, None, None) == vp.VP_EINVAL  # NULL ticket
+    assert lib.vp_submit(None, None, ctypes.byref(ticket)) == vp.VP_EINVAL  # NULL context and job
+    assert lib.vp_poll(None, 1, None) == vp.VP_EINVAL
+    assert lib.vp_serve_stats(None, None, None) == vp.VP_EINVAL
+    assert lib.vp_job_footprint(None, None, None) == vp.VP_EINVAL
+    assert lib.vp_subtract(None, None, None, 1, 1, None, None) == vp.VP_EINVAL
+    assert lib.vp_destroy_obs(None) == vp.VP_EINVAL
+    assert lib.vp_destroy_sky(None) == vp.VP_EINVAL
+    assert lib.vp_profile(None, 1) == vp.VP_EINVAL
+    assert lib.vp_profile_read(None, None, None) == vp.VP_EINVAL
+
+
 def test_peel_null_arguments_are_rejected_before_any_device_work():
     lib = vp.load()
     assert lib.vp_peel(None, None, None, None, None, 4, 1, 0, 0, None, None, None) == vp.VP_EINVAL
