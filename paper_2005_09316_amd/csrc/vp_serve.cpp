@@ -172,8 +172,9 @@ void HipExecutor::publish_tiles(JobExt &x) {
 }
 
 // Shapelet phase: every point/Gaussian tile of the job is written back; its
-// shapelet tiles add to them (the newer sequence number makes the shapelet
-// kernel's workers drop cached lines of the visibilities).
+// shapelet tiles add to them.  They run in a launch of ring 1's kernel that
+// starts after the ring-0 launch that wrote those tiles has ended (the two
+// kernels share one stream), so no worker holds an older copy of them.
 void HipExecutor::publish_shp(JobExt &x) {
   ServeJobDesc &desc = H->jobs[x.slot];
   x.seq_shp = next_seq++;
