@@ -50,15 +50,19 @@ static int check_job(vp_ctx *ctx, const vp_job *job) {
   return VP_OK;
 }
 
-// Units behind one ring entry.  Tiles: about four entries per workgroup of
-// the kernel for the job's whole phase (their costs vary), at most kMaxRun
-// tiles (so that jobs queued behind wait for runs of bounded length).  Table
-// units cost alike and little (a few microseconds each): kTableEntries
-// entries per phase, since every claim is a device-wide atomic and the claims
-// of a burst are served one after another.
+// Units behind one ring entry.  Every claim is a device-wide atomic, and the
+// claims of a burst are served one after another, so a phase gets as few
+// entries as its balance allows.  Tiles: one per entry while the phase has no
+// more tiles than the kernel has workgroups; one entry per workgroup up to
+// four times that; beyond, four entries per workgroup (their costs vary, and
+// the last ones set the phase's end) of at most kMaxRun tiles (so that jobs
+// queued behind wait for runs of bounded length).  Table units cost alike and
+// little (a few microseconds each): kTableEntries entries per phase.
 constexpr int64_t kMaxRun = 64;
 static int64_t run_length(int64_t units, int grid) {
-  return std::max<int64_t>(1, std::min<int64_t>(kMaxRun, units / (4 * (int64_t)std::max(grid, 1))));
+  const int64_t g = std::max(grid, 1);
+  const int64_t e = units <= g ? std::max<int64_t>(units, 1) : (units <= 4 * g ? g : 4 * g);  // entries
+  return std::max<int64_t>(1, std::min<int64_t>(kMaxRun, (units + e - 1) / e));
 }
 constexpr int64_t kTableEntries = 64;
 static int64_t table_run_length(int64_t units) {
