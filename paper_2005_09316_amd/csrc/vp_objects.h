@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <set>
 #include <utility>
@@ -170,7 +171,8 @@ struct vp_ctx {
   bool profile = false;
   std::mutex prof_mu;
   std::vector<vp::ProfRecord> prof_pending;
-  vp::Scheduler *sched = nullptr;
+  // created by the first vp_submit (under mu), read by vp_poll without it
+  std::atomic<vp::Scheduler *> sched{nullptr};
   vp::PeelWork *peel = nullptr;
   float *lut = nullptr;    // basis table of VP_PREC_LUT, built at its first use (guarded by mu)
   vp::DeviceMem lut_mem;

@@ -458,17 +458,17 @@ void HipExecutor::teardown() {
 }
 
 bool serve_pending(vp_ctx *ctx) {
-  Scheduler *s = ctx->sched;
+  Scheduler *s = ctx->sched.load(std::memory_order_acquire);
   return s && s->core->pending();
 }
 
 void serve_shutdown(vp_ctx *ctx) {
-  Scheduler *s = ctx->sched;
+  Scheduler *s = ctx->sched.exchange(nullptr, std::memory_order_acq_rel);
   if (!s) return;
+  // not under ctx->mu: the scheduler thread takes it while retiring jobs
   delete s->core;  // drains (nothing is pending here) and stops the thread
   s->ex.teardown();
   delete s;
-  ctx->sched = nullptr;
 }
 
 }  // namespace vp
@@ -499,7 +499,8 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
   Scheduler *s = nullptr;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (!ctx->sched) {
+    s = ctx->sched.load(std::memory_order_relaxed);
+    if (!s) {
       Scheduler *n = new Scheduler();
       rc = n->ex.init(ctx);
       if (rc != VP_OK) {
@@ -507,9 +508,9 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
         return rc;
       }
       n->core = new ServeCore(&n->ex, ctx->budget);
-      ctx->sched = n;
+      ctx->sched.store(n, std::memory_order_release);
+      s = n;
     }
-    s = ctx->sched;
   }
   JobExt *x = new JobExt();
   x->job = *job;
@@ -557,7 +558,7 @@ int vp_submit(vp_ctx *ctx, const vp_job *job, uint64_t *ticket) {
 
 int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res) {
   if (!ctx || !res) return set_error(VP_EINVAL, "NULL context or result");
-  Scheduler *s = ctx->sched;
+  Scheduler *s = ctx->sched.load(std::memory_order_acquire);
   if (!s) return set_error(VP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
   CoreJob j;
   const int rc = s->core->poll(ticket, &j);
@@ -575,7 +576,7 @@ int vp_poll(vp_ctx *ctx, uint64_t ticket, vp_job_result *res) {
 
 int vp_serve_stats(vp_ctx *ctx, uint64_t *launches, double *resident_ms) {
   if (!ctx || !launches || !resident_ms) return set_error(VP_EINVAL, "NULL argument");
-  Scheduler *s = ctx->sched;
+  Scheduler *s = ctx->sched.load(std::memory_order_acquire);
   if (!s) {
     *launches = 0;
     *resident_ms = 0.0;
