@@ -41,6 +41,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "vp_internal.h"
 
@@ -1172,10 +1173,13 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) 
 // shapelet kernel, FP64 path (vector ALU)
 // ---------------------------------------------------------------------------
 
-// One thread per (row, channel) visibility of the tile; the second axis's
-// Hermite values live in registers (NB + 1 of them, NB the order bucket), the
-// first axis's recurrence advances with the n1 loop, and each n1 row of the
-// signed coefficient matrix is read as wave-uniform loads.
+// One thread per row of the tile, for the tile's kShpChan channels.  The
+// second axis is taken in chunks of orders whose Hermite values sit in
+// registers; per chunk the matching columns of the signed coefficient matrix
+// are staged in LDS and each row n1 of them is dotted with those values while
+// the first axis's recurrence advances with n1.  The recurrence path takes
+// the four channels together (16-order chunks), the lookup-table variant one
+// channel at a time (32-order chunks).
 // Lookup-table variant of the basis (the paper's simulator interpolates a
 // 1-D table of the basis, Sec. 3.2): phi_n at x_i = i dx, 0 <= i <= kLutSamples,
 // dx = kLutXMax / kLutSamples, FP32, rows of kLutStride orders; phi_n(-x) =
@@ -1224,8 +1228,12 @@ __device__ __forceinline__ double lut_at(const LutPos &q, int n) {
   return (double)((n & 1) ? q.odd * v : v);
 }
 
+// Second-axis orders per chunk of the FP64 recurrence path: the values of a
+// chunk for the tile's four channels (4 x 16 FP64) stay in registers.
+constexpr int kF64Chunk = 16;
+
 template <bool LUT>
-__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(3))) void k_shp_fp64(TileArgs a) {
+__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(LUT ? 3 : 2))) void k_shp_fp64(TileArgs a) {
   constexpr int KB = kShpChan;
   // one 32-column chunk of the signed coefficient matrix (rows 0 .. N - m0),
   // staged in LDS for the whole workgroup and read as broadcasts: from
@@ -1250,94 +1258,198 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(3))) 
     const double am = fma(fr[0], u, fma(fr[1], v, fr[2] * w));
     const double bm = fma(fr[3], u, fma(fr[4], v, fr[5] * w));
     const double t0 = fma(fr[6], u, fma(fr[7], v, fr[8] * w));
-    // The second axis in chunks of 32 orders (its recurrence carried across
-    // chunks, per channel); per chunk and channel the first axis is walked
-    // from order 0 and each row n1 is dotted with the chunk's part of row n1
-    // of the signed coefficient matrix.  32 values per lane stay in registers.
-    const double *C = a.t.c64 + a.t.c64_off[j];
-    const int ld = a.t.c64_ld[j];
-    double bn[KB], bm1[KB], xr[KB], xi[KB];  // per channel: second-axis recurrence, sums
-#pragma unroll
-    for (int c = 0; c < KB; ++c) {
-      const double xb = a.fk[k0 + c] * bm;
-      bn[c] = kPiM14 * exp(-0.5 * xb * xb);
-      bm1[c] = xr[c] = xi[c] = 0.0;
-    }
-    for (int ch = 0; 32 * ch <= N; ++ch) {
-      const int m0 = 32 * ch;
-      __syncthreads();  // the previous chunk is no longer read
-      for (int i = tid; i < (N - m0 + 1) * 32; i += kTileRows) {
-        const int col = m0 + (i & 31);
-        sC[i] = col < ld ? C[(int64_t)(i >> 5) * ld + col] : 0.0;
-      }
-      __syncthreads();
+    if constexpr (!LUT) {
+      // The second axis in chunks of kF64Chunk orders (its recurrence carried
+      // across chunks, per channel); per chunk the first axis is walked from
+      // order 0 for all of the tile's channels at once, and each row n1 is
+      // dotted with the chunk's part of row n1 of the signed coefficient
+      // matrix.  Every coefficient read from LDS (a broadcast to all lanes)
+      // feeds the tile's four channels: with one channel per read the LDS
+      // return path, not the FP64 units, set the pace.  Channels past the
+      // last (a ragged tile) are computed on the padded frequency table and
+      // not written.
+      const double *C = a.t.c64 + a.t.c64_off[j];
+      const int ld = a.t.c64_ld[j];
+      double bn[KB], bm1[KB], xr[KB], xi[KB], pa0[KB];  // per channel
 #pragma unroll
       for (int c = 0; c < KB; ++c) {
-        if (c >= nc) break;
         const double f = a.fk[k0 + c];
-        const double xa = f * am, xb = f * bm;
-        const double sxa = 1.41421356237309504880 * xa, sxb = 1.41421356237309504880 * xb;
-        LutPos qa, qb;
-        if constexpr (LUT) {
-          qa = lut_pos(a.lut, xa);
-          qb = lut_pos(a.lut, xb);
+        const double xb = f * bm, xa = f * am;
+        bn[c] = kPiM14 * exp(-0.5 * xb * xb);
+        pa0[c] = kPiM14 * exp(-0.5 * xa * xa);
+        bm1[c] = xr[c] = xi[c] = 0.0;
+      }
+      for (int ch = 0; kF64Chunk * ch <= N; ++ch) {
+        const int m0 = kF64Chunk * ch;
+        __syncthreads();  // the previous chunk is no longer read
+        for (int i = tid; i < (N - m0 + 1) * kF64Chunk; i += kTileRows) {
+          const int col = m0 + (i % kF64Chunk);
+          sC[i] = col < ld ? C[(int64_t)(i / kF64Chunk) * ld + col] : 0.0;
         }
-        double pb[32];
+        __syncthreads();
+        double pb[KB][kF64Chunk];
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
-          if constexpr (LUT) {
-            pb[i] = m0 + i <= kNmaxLimit ? lut_at(qb, m0 + i) : 0.0;
-          } else {
-            pb[i] = bn[c];
+        for (int c = 0; c < KB; ++c) {
+          const double sxb = 1.41421356237309504880 * (a.fk[k0 + c] * bm);
+#pragma unroll
+          for (int i = 0; i < kF64Chunk; ++i) {
+            pb[c][i] = bn[c];
             const double nx = herm_step<double>(sxb, bn[c], bm1[c], m0 + i);  // orders <= 127: table size
             bm1[c] = bn[c];
             bn[c] = nx;
           }
         }
-        double pa, pam1 = 0.0;
-        if constexpr (LUT)
-          pa = lut_at(qa, 0);
-        else
-          pa = kPiM14 * exp(-0.5 * xa * xa);
-        for (int n1 = 0; n1 <= N - m0; ++n1) {
-          const double *Cr = sC + n1 * 32;
-          double te = 0.0, to = 0.0;
+        double pa[KB], pam1[KB], sxa[KB];
 #pragma unroll
-          for (int b8 = 0; b8 < 4; ++b8) {
-            if (8 * b8 <= N - m0 - n1) {
+        for (int c = 0; c < KB; ++c) {
+          pa[c] = pa0[c];
+          pam1[c] = 0.0;
+          sxa[c] = 1.41421356237309504880 * (a.fk[k0 + c] * am);
+        }
+        // one row n1: its dots with the chunk's second-axis values, folded
+        // with the first axis into the real or imaginary sums by the parity
+        // of n1 (rows are taken in pairs, so the parity is a constant)
+        auto row = [&](int n1, auto ODD) {
+          const double *Cr = sC + n1 * kF64Chunk;
+          double te[KB], to[KB];
+#pragma unroll
+          for (int b8 = 0; b8 < kF64Chunk / 8; ++b8) {
+            if (b8 == 0 || 8 * b8 <= N - m0 - n1) {
 #pragma unroll
               for (int e = 0; e < 8; e += 2) {
-                te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
-                to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
+                const double ce = Cr[8 * b8 + e], co = Cr[8 * b8 + e + 1];
+#pragma unroll
+                for (int c = 0; c < KB; ++c) {
+                  if (b8 == 0 && e == 0) {
+                    te[c] = ce * pb[c][0];
+                    to[c] = co * pb[c][1];
+                  } else {
+                    te[c] = fma(ce, pb[c][8 * b8 + e], te[c]);
+                    to[c] = fma(co, pb[c][8 * b8 + e + 1], to[c]);
+                  }
+                }
               }
             }
           }
-          if (n1 & 1) {
-            xr[c] = fma(pa, to, xr[c]);
-            xi[c] = fma(pa, te, xi[c]);
-          } else {
-            xr[c] = fma(pa, te, xr[c]);
-            xi[c] = fma(pa, to, xi[c]);
+#pragma unroll
+          for (int c = 0; c < KB; ++c) {
+            if constexpr (decltype(ODD)::value) {
+              xr[c] = fma(pa[c], to[c], xr[c]);
+              xi[c] = fma(pa[c], te[c], xi[c]);
+            } else {
+              xr[c] = fma(pa[c], te[c], xr[c]);
+              xi[c] = fma(pa[c], to[c], xi[c]);
+            }
+            const double nx = herm_step<double>(sxa[c], pa[c], pam1[c], n1);
+            pam1[c] = pa[c];
+            pa[c] = nx;
           }
+        };
+        for (int n1 = 0; n1 <= N - m0; n1 += 2) {
+          row(n1, std::integral_constant<bool, false>());
+          if (n1 + 1 <= N - m0) row(n1 + 1, std::integral_constant<bool, true>());
+        }
+      }
+  #pragma unroll
+      for (int c = 0; c < KB; ++c) {
+        if (c >= nc) break;
+        const double f = a.fk[k0 + c];
+        double cs, sn;
+        turns_sincos_f64(t0 * f, cs, sn);
+        const double S = a.d.flux64[(int64_t)(a.P + a.G + j) * a.Kpad + k0 + c];
+        acc_re[c] += S * (xr[c] * cs - xi[c] * sn);
+        acc_im[c] += S * (xr[c] * sn + xi[c] * cs);
+      }
+    } else {
+      // The second axis in chunks of 32 orders (its recurrence carried across
+      // chunks, per channel); per chunk and channel the first axis is walked
+      // from order 0 and each row n1 is dotted with the chunk's part of row n1
+      // of the signed coefficient matrix.  32 values per lane stay in registers.
+      const double *C = a.t.c64 + a.t.c64_off[j];
+      const int ld = a.t.c64_ld[j];
+      double bn[KB], bm1[KB], xr[KB], xi[KB];  // per channel: second-axis recurrence, sums
+  #pragma unroll
+      for (int c = 0; c < KB; ++c) {
+        const double xb = a.fk[k0 + c] * bm;
+        bn[c] = kPiM14 * exp(-0.5 * xb * xb);
+        bm1[c] = xr[c] = xi[c] = 0.0;
+      }
+      for (int ch = 0; 32 * ch <= N; ++ch) {
+        const int m0 = 32 * ch;
+        __syncthreads();  // the previous chunk is no longer read
+        for (int i = tid; i < (N - m0 + 1) * 32; i += kTileRows) {
+          const int col = m0 + (i & 31);
+          sC[i] = col < ld ? C[(int64_t)(i >> 5) * ld + col] : 0.0;
+        }
+        __syncthreads();
+  #pragma unroll
+        for (int c = 0; c < KB; ++c) {
+          if (c >= nc) break;
+          const double f = a.fk[k0 + c];
+          const double xa = f * am, xb = f * bm;
+          const double sxa = 1.41421356237309504880 * xa, sxb = 1.41421356237309504880 * xb;
+          LutPos qa, qb;
           if constexpr (LUT) {
-            pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
-          } else {
-            const double nx = herm_step<double>(sxa, pa, pam1, n1);
-            pam1 = pa;
-            pa = nx;
+            qa = lut_pos(a.lut, xa);
+            qb = lut_pos(a.lut, xb);
+          }
+          double pb[32];
+  #pragma unroll
+          for (int i = 0; i < 32; ++i) {
+            if constexpr (LUT) {
+              pb[i] = m0 + i <= kNmaxLimit ? lut_at(qb, m0 + i) : 0.0;
+            } else {
+              pb[i] = bn[c];
+              const double nx = herm_step<double>(sxb, bn[c], bm1[c], m0 + i);  // orders <= 127: table size
+              bm1[c] = bn[c];
+              bn[c] = nx;
+            }
+          }
+          double pa, pam1 = 0.0;
+          if constexpr (LUT)
+            pa = lut_at(qa, 0);
+          else
+            pa = kPiM14 * exp(-0.5 * xa * xa);
+          for (int n1 = 0; n1 <= N - m0; ++n1) {
+            const double *Cr = sC + n1 * 32;
+            double te = 0.0, to = 0.0;
+  #pragma unroll
+            for (int b8 = 0; b8 < 4; ++b8) {
+              if (8 * b8 <= N - m0 - n1) {
+  #pragma unroll
+                for (int e = 0; e < 8; e += 2) {
+                  te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
+                  to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
+                }
+              }
+            }
+            if (n1 & 1) {
+              xr[c] = fma(pa, to, xr[c]);
+              xi[c] = fma(pa, te, xi[c]);
+            } else {
+              xr[c] = fma(pa, te, xr[c]);
+              xi[c] = fma(pa, to, xi[c]);
+            }
+            if constexpr (LUT) {
+              pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
+            } else {
+              const double nx = herm_step<double>(sxa, pa, pam1, n1);
+              pam1 = pa;
+              pa = nx;
+            }
           }
         }
       }
-    }
-#pragma unroll
-    for (int c = 0; c < KB; ++c) {
-      if (c >= nc) break;
-      const double f = a.fk[k0 + c];
-      double cs, sn;
-      turns_sincos_f64(t0 * f, cs, sn);
-      const double S = a.d.flux64[(int64_t)(a.P + a.G + j) * a.Kpad + k0 + c];
-      acc_re[c] += S * (xr[c] * cs - xi[c] * sn);
-      acc_im[c] += S * (xr[c] * sn + xi[c] * cs);
+  #pragma unroll
+      for (int c = 0; c < KB; ++c) {
+        if (c >= nc) break;
+        const double f = a.fk[k0 + c];
+        double cs, sn;
+        turns_sincos_f64(t0 * f, cs, sn);
+        const double S = a.d.flux64[(int64_t)(a.P + a.G + j) * a.Kpad + k0 + c];
+        acc_re[c] += S * (xr[c] * cs - xi[c] * sn);
+        acc_im[c] += S * (xr[c] * sn + xi[c] * cs);
+      }
     }
   }
   if (!valid) return;
