@@ -69,11 +69,17 @@ def _case(name):
     if name == "nmax-limit":
         return synth.make_config(0, n_tiles=16, n_time=2, n_chan=5, n_point=3, n_gauss=2,
                                  shapelet_nmax=[96, 0, 1, 31, 32, 63, 64])
+    if name == "nmax-chunks":
+        # orders on either side of every 16-order boundary below 96 (the FP64
+        # kernel's second-axis chunks; 32-order blocks elsewhere), 7 channels
+        # (ragged against 4-channel tiles)
+        return synth.make_config(0, n_tiles=16, n_time=2, n_chan=7, n_point=3, n_gauss=2,
+                                 shapelet_nmax=[15, 16, 17, 47, 48, 49, 79, 80, 81])
     raise KeyError(name)
 
 
 CASES = ["tiny", "mwa-mid", "fornax-mid", "lobes-only", "mwa-nonuniform", "mwa-descending", "mwa-jittered",
-         "nmax-limit"]
+         "nmax-limit", "nmax-chunks"]
 _REF = {}
 
 
