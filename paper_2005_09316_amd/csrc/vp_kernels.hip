@@ -1221,11 +1221,29 @@ __device__ __forceinline__ LutPos lut_pos(const float *T, double x) {
   return q;
 }
 
-__device__ __forceinline__ double lut_at(const LutPos &q, int n) {
-  if (!q.in) return 0.0;
-  const float v0 = q.r0[n], v1 = q.r0[n + kLutStride];
-  const float v = fmaf(q.fr, v1 - v0, v0);
-  return (double)((n & 1) ? q.odd * v : v);
+// Orders n0 .. n0 + 31 of the basis at q: linear interpolation between the
+// two bracketing rows, the sign (-1)^n for x < 0, zero past kNmaxLimit and
+// beyond the table.  The rows are read with 16-byte loads: a lane's orders
+// are contiguous in its rows, and one 4-byte load per order made every load
+// instruction touch a cache line per lane.  n0 is a multiple of 32; rows are 16-byte aligned (kLutStride x 4 B),
+// and orders past kLutStride read the following row (inside the table, which
+// has a spare row) before they are masked.
+__device__ __forceinline__ void lut_chunk(const LutPos &q, int n0, float (&v)[32]) {
+  const float4 *p0 = (const float4 *)(q.r0 + n0), *p1 = (const float4 *)(q.r0 + kLutStride + n0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float4 a = p0[k], b = p1[k];
+    v[4 * k] = fmaf(q.fr, b.x - a.x, a.x);
+    v[4 * k + 1] = fmaf(q.fr, b.y - a.y, a.y);
+    v[4 * k + 2] = fmaf(q.fr, b.z - a.z, a.z);
+    v[4 * k + 3] = fmaf(q.fr, b.w - a.w, a.w);
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int n = n0 + i;
+    const float x = (n & 1) ? q.odd * v[i] : v[i];
+    v[i] = q.in && n <= kNmaxLimit ? x : 0.0f;
+  }
 }
 
 // Second-axis orders per chunk of the FP64 recurrence path: the values of a
@@ -1233,7 +1251,7 @@ __device__ __forceinline__ double lut_at(const LutPos &q, int n) {
 constexpr int kF64Chunk = 16;
 
 template <bool LUT>
-__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(LUT ? 3 : 2))) void k_shp_fp64(TileArgs a) {
+__global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(2))) void k_shp_fp64(TileArgs a) {
   constexpr int KB = kShpChan;
   // one 32-column chunk of the signed coefficient matrix (rows 0 .. N - m0),
   // staged in LDS for the whole workgroup and read as broadcasts: from
@@ -1350,7 +1368,7 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(LUT ?
           if (n1 + 1 <= N - m0) row(n1 + 1, std::integral_constant<bool, true>());
         }
       }
-  #pragma unroll
+#pragma unroll
       for (int c = 0; c < KB; ++c) {
         if (c >= nc) break;
         const double f = a.fk[k0 + c];
@@ -1361,19 +1379,17 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(LUT ?
         acc_im[c] += S * (xr[c] * sn + xi[c] * cs);
       }
     } else {
-      // The second axis in chunks of 32 orders (its recurrence carried across
-      // chunks, per channel); per chunk and channel the first axis is walked
-      // from order 0 and each row n1 is dotted with the chunk's part of row n1
-      // of the signed coefficient matrix.  32 values per lane stay in registers.
+      // Lookup-table basis: the second axis in chunks of 32 orders, one
+      // channel at a time; per chunk and channel each row n1 is dotted with
+      // the chunk's part of row n1 of the signed coefficient matrix (staged in
+      // LDS), and the first axis's table values are read 32 rows at a time,
+      // all in flight before the rows that use them: a table read per row,
+      // waited on by that row, left the kernel waiting on memory.
       const double *C = a.t.c64 + a.t.c64_off[j];
       const int ld = a.t.c64_ld[j];
-      double bn[KB], bm1[KB], xr[KB], xi[KB];  // per channel: second-axis recurrence, sums
-  #pragma unroll
-      for (int c = 0; c < KB; ++c) {
-        const double xb = a.fk[k0 + c] * bm;
-        bn[c] = kPiM14 * exp(-0.5 * xb * xb);
-        bm1[c] = xr[c] = xi[c] = 0.0;
-      }
+      double xr[KB], xi[KB];
+#pragma unroll
+      for (int c = 0; c < KB; ++c) xr[c] = xi[c] = 0.0;
       for (int ch = 0; 32 * ch <= N; ++ch) {
         const int m0 = 32 * ch;
         __syncthreads();  // the previous chunk is no longer read
@@ -1382,65 +1398,50 @@ __global__ __launch_bounds__(kTileRows) __attribute__((amdgpu_waves_per_eu(LUT ?
           sC[i] = col < ld ? C[(int64_t)(i >> 5) * ld + col] : 0.0;
         }
         __syncthreads();
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < KB; ++c) {
           if (c >= nc) break;
           const double f = a.fk[k0 + c];
-          const double xa = f * am, xb = f * bm;
-          const double sxa = 1.41421356237309504880 * xa, sxb = 1.41421356237309504880 * xb;
-          LutPos qa, qb;
-          if constexpr (LUT) {
-            qa = lut_pos(a.lut, xa);
-            qb = lut_pos(a.lut, xb);
-          }
+          const LutPos qa = lut_pos(a.lut, f * am), qb = lut_pos(a.lut, f * bm);
           double pb[32];
-  #pragma unroll
-          for (int i = 0; i < 32; ++i) {
-            if constexpr (LUT) {
-              pb[i] = m0 + i <= kNmaxLimit ? lut_at(qb, m0 + i) : 0.0;
-            } else {
-              pb[i] = bn[c];
-              const double nx = herm_step<double>(sxb, bn[c], bm1[c], m0 + i);  // orders <= 127: table size
-              bm1[c] = bn[c];
-              bn[c] = nx;
-            }
+          {
+            float pbf[32];
+            lut_chunk(qb, m0, pbf);
+#pragma unroll
+            for (int i = 0; i < 32; ++i) pb[i] = (double)pbf[i];
           }
-          double pa, pam1 = 0.0;
-          if constexpr (LUT)
-            pa = lut_at(qa, 0);
-          else
-            pa = kPiM14 * exp(-0.5 * xa * xa);
-          for (int n1 = 0; n1 <= N - m0; ++n1) {
-            const double *Cr = sC + n1 * 32;
-            double te = 0.0, to = 0.0;
-  #pragma unroll
-            for (int b8 = 0; b8 < 4; ++b8) {
-              if (8 * b8 <= N - m0 - n1) {
-  #pragma unroll
-                for (int e = 0; e < 8; e += 2) {
-                  te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
-                  to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
+          for (int r0 = 0; r0 <= N - m0; r0 += 32) {
+            float pa[32];  // rows past N - m0 are read but not used
+            lut_chunk(qa, r0, pa);
+#pragma unroll
+            for (int r = 0; r < 32; ++r) {
+              const int n1 = r0 + r;  // r0 is a multiple of 32: n1 has the parity of r
+              if (n1 > N - m0) break;
+              const double *Cr = sC + n1 * 32;
+              double te = 0.0, to = 0.0;
+#pragma unroll
+              for (int b8 = 0; b8 < 4; ++b8) {
+                if (8 * b8 <= N - m0 - n1) {
+#pragma unroll
+                  for (int e = 0; e < 8; e += 2) {
+                    te = fma(Cr[8 * b8 + e], pb[8 * b8 + e], te);
+                    to = fma(Cr[8 * b8 + e + 1], pb[8 * b8 + e + 1], to);
+                  }
                 }
               }
-            }
-            if (n1 & 1) {
-              xr[c] = fma(pa, to, xr[c]);
-              xi[c] = fma(pa, te, xi[c]);
-            } else {
-              xr[c] = fma(pa, te, xr[c]);
-              xi[c] = fma(pa, to, xi[c]);
-            }
-            if constexpr (LUT) {
-              pa = n1 < kNmaxLimit ? lut_at(qa, n1 + 1) : 0.0;
-            } else {
-              const double nx = herm_step<double>(sxa, pa, pam1, n1);
-              pam1 = pa;
-              pa = nx;
+              const double pv = (double)pa[r];
+              if (r & 1) {
+                xr[c] = fma(pv, to, xr[c]);
+                xi[c] = fma(pv, te, xi[c]);
+              } else {
+                xr[c] = fma(pv, te, xr[c]);
+                xi[c] = fma(pv, to, xi[c]);
+              }
             }
           }
         }
       }
-  #pragma unroll
+#pragma unroll
       for (int c = 0; c < KB; ++c) {
         if (c >= nc) break;
         const double f = a.fk[k0 + c];
