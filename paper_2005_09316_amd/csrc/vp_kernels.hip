@@ -1225,9 +1225,10 @@ __device__ __forceinline__ LutPos lut_pos(const float *T, double x) {
 // two bracketing rows, the sign (-1)^n for x < 0, zero past kNmaxLimit and
 // beyond the table.  The rows are read with 16-byte loads: a lane's orders
 // are contiguous in its rows, and one 4-byte load per order made every load
-// instruction touch a cache line per lane.  n0 is a multiple of 32; rows are 16-byte aligned (kLutStride x 4 B),
-// and orders past kLutStride read the following row (inside the table, which
-// has a spare row) before they are masked.
+// instruction touch a cache line per lane.  n0 is a multiple of 32 and rows
+// are 16-byte aligned (kLutStride x 4 B); orders past kLutStride read the
+// following row (inside the table, which has a spare row) before they are
+// masked.
 __device__ __forceinline__ void lut_chunk(const LutPos &q, int n0, float (&v)[32]) {
   const float4 *p0 = (const float4 *)(q.r0 + n0), *p1 = (const float4 *)(q.r0 + kLutStride + n0);
 #pragma unroll
